@@ -1,0 +1,105 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// liblogfx.  Not part of the public ABI (include/logfx.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace logfx {
+
+constexpr int kWave = 64;
+constexpr int kMaxRadius = 4;                        // masks up to 9 x 9
+constexpr int kMaxOrbits = (kMaxRadius + 1) * (kMaxRadius + 2) / 2;
+
+// Halo (in L-response pixels) that each pass keeps around its output tile.
+//  pass 1: the zero-crossing test needs L at +-1.
+//  pass 2: median (+-2) <- local std (+-1) <- zero crossing (+-1) = +-4.
+constexpr int kHalo1 = 1;
+constexpr int kHalo2 = 4;
+
+// Orbit index of the D4 orbit {(+-i, +-j), (+-j, +-i)}, 0 <= j <= i.
+__host__ __device__ constexpr int orbit_index(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Orbit taps of both masks, in integer grid units.  The integer path keeps
+// them as int (they fit 24-bit signed); the FP64 path as double.
+struct OrbitTapsI { int k[2][kMaxOrbits]; };
+struct OrbitTapsD { double k[2][kMaxOrbits]; };
+
+// Device-side statistics written by the finalize kernel (LoG grid units).
+struct DevStats {
+    double sum[2];     // sum Z_j
+    double sumsq[2];   // sum Z_j^2
+    double sigma[2];   // unbiased global standard deviation of Z_j
+    double thresh[2];  // T_j
+    double thr72[2];   // 72 T_j^2 (compared with 9 sum z^2 - (sum z)^2)
+    long long zc[2];   // pixels with Z_j != 0
+};
+
+struct ImageDesc {
+    const void *data;
+    long long H, W, pitch;
+    int dtype;   // 0 u8, 1 u16
+};
+
+template <class Taps>
+struct Pass1Args {
+    ImageDesc img;
+    Taps taps;
+    double zc_thr[2];      // zero-crossing threshold per mask, grid units
+    int rows;              // output rows per wave strip
+    int waves;             // waves per workgroup (tile width = waves * (64 - 2 halo))
+    int tiles_x;           // tiles across the image
+    int ntiles;            // tiles in the image (= grid size)
+    double *partials;      // [ntiles][4]: sum Z1, sum Z2, sum Z1^2, sum Z2^2
+    long long *counts;     // [ntiles][2]: crossings of mask 1, mask 2
+    // Optional FP64 maps (LoG units = grid units * unit[j]); NULL to skip.
+    double *dbgL[2];
+    double *dbgZ[2];
+    double unit[2];
+};
+
+template <class Taps>
+struct Pass2Args {
+    ImageDesc img;
+    Taps taps;
+    double zc_thr[2];
+    int rows;
+    int waves;
+    int tiles_x;
+    int ntiles;
+    const DevStats *stats;  // thresholds from the finalize kernel
+    uint8_t *out;           // H x W, pitch out_pitch
+    long long out_pitch;
+    int smooth;             // 0 = E, 1 = hybrid median of E
+    int median_size;        // 3 or 5
+    int *counts;            // [ntiles][2]: E pixels, output pixels
+};
+
+struct FinalizeArgs {
+    const double *partials;
+    const long long *counts;
+    int ntiles;
+    long long n;           // pixels
+    int std_mode;          // 0 relative, 1 absolute
+    double std_k;
+    double abs_thr[2];     // absolute threshold per mask in grid units (std_mode 1)
+    DevStats *stats;
+};
+
+// Launchers (defined in logfx_kernels.hip).  They return hipSuccess or the
+// launch error.  ra <= rb are the radii of the two masks.
+hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, hipStream_t s);
+hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, hipStream_t s);
+hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, hipStream_t s);
+hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+
+// LDS bytes of one workgroup.
+inline size_t lds_bytes(int waves, int rows, int halo, int rb) {
+    const int width = waves * (kWave - 2 * halo) + 2 * halo + 2 * rb;
+    const int height = rows + 2 * halo + 2 * rb;
+    const int stride = (width + 1) & ~1;
+    return (size_t)stride * height * sizeof(uint16_t);
+}
+
+}  // namespace logfx

@@ -1,0 +1,566 @@
+// HIP kernels of liblogfx for gfx950 (CDNA4, wave64).
+//
+// The pipeline (Tejaswi et al., arXiv:1304.3992, Sec. 4.1):
+//   L_j = LoG_j * I (eq. (1) masks), Z_j = zero-crossing strength of L_j
+//   (Sec. 3.2), E_j = [3x3 deviation of Z_j > T_j] (eq. (2)), E = E_1 | E_2,
+//   F = hybrid_median(E) (Sec. 3.4).
+// T_j depends on the global deviation of Z_j, a grid-wide quantity, so the
+// work runs as   pass 1 (LoG, Z, per-tile sums) -> finalize (T_j) ->
+// pass 2 (LoG and Z again with a wider halo, local deviation, OR, median).
+//
+// Work decomposition.  A workgroup owns an output tile of `waves` wave-wide
+// column strips side by side, `rows` rows tall; the input tile plus halo is
+// staged once in LDS as u16 with clamp-to-edge coordinates.  Each lane owns
+// one column and walks down the rows, keeping a ring of 2R+1 rows of
+// horizontal pair sums in registers.  Horizontal neighbours of later
+// stages come from the adjacent lanes (ds_bpermute with clamped source
+// lanes), so stage-wise clamp-to-edge borders come for free.  The extracted
+// bits of a row are a 64-bit wave ballot; the hybrid median of those bits is
+// computed bit-sliced on the scalar unit, 64 pixels per instruction.
+//
+// Exactness.  Mask taps are integers k on a power-of-two grid, and the LoG
+// is evaluated on D4 orbit sums of pixels: L = sum_o k_o * O_o.  Every sum is
+// exact (int32 when sum|k| (2^bits - 1) < 2^30, else FP64 below 2^52), so L
+// and Z agree bit for bit with any exact evaluation.
+#include "logfx_internal.h"
+
+namespace logfx {
+namespace {
+
+// ----------------------------------------------------------------- helpers
+__device__ inline int xcd_remap(int b, int n) {
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of tiles so neighbouring tiles (which share halo rows
+    // and columns) meet in the same L2.
+    constexpr int X = 8;
+    const int q = n / X, rem = n % X;
+    const int xcd = b % X, slot = b / X;
+    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
+__device__ inline long long clampll(long long v, long long lo, long long hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+template <class T>
+__device__ inline void load_rows(uint16_t *lds, int stride, const T *img, long long pitch,
+                                 long long H, long long W, long long ry0, long long rx0, int RH,
+                                 int RW) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    for (int r = wave; r < RH; r += nw) {
+        const T *src = img + clampll(ry0 + r, 0, H - 1) * pitch;
+        uint16_t *dst = lds + r * stride;
+        for (int c = lane; c < RW; c += kWave) dst[c] = (uint16_t)src[clampll(rx0 + c, 0, W - 1)];
+    }
+}
+
+__device__ inline void load_tile(uint16_t *lds, int stride, const ImageDesc &img, long long ry0,
+                                 long long rx0, int RH, int RW) {
+    if (img.dtype == 0)
+        load_rows(lds, stride, (const uint8_t *)img.data, img.pitch, img.H, img.W, ry0, rx0, RH, RW);
+    else
+        load_rows(lds, stride, (const uint16_t *)img.data, img.pitch, img.H, img.W, ry0, rx0, RH,
+                  RW);
+}
+
+__device__ inline int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+__device__ inline double bperm(int addr, double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(bperm(addr, hi), bperm(addr, lo));
+}
+
+// Accumulator policies: exact int32 or exact FP64 LoG sums.
+template <class Acc> struct AccOps;
+template <> struct AccOps<int> {
+    using Taps = OrbitTapsI;
+    static __device__ int mac(int k, int o, int acc) { return acc + __mul24(k, o); }
+    static __device__ double range(int mx, int mn) { return (double)(mx - mn); }
+    static __device__ double to_d(int v) { return (double)v; }
+};
+template <> struct AccOps<double> {
+    using Taps = OrbitTapsD;
+    static __device__ double mac(double k, int o, double acc) { return __fma_rn(k, (double)o, acc); }
+    static __device__ double range(double mx, double mn) { return mx - mn; }
+    static __device__ double to_d(double v) { return v; }
+};
+
+// One row of horizontal pair sums at the lane's column: h[0] = I(x),
+// h[j] = I(x - j) + I(x + j).
+template <int RB>
+__device__ inline void load_hrow(const uint16_t *p, int (&h)[RB + 1]) {
+    h[0] = p[0];
+#pragma unroll
+    for (int j = 1; j <= RB; ++j) h[j] = (int)p[-j] + (int)p[j];
+}
+
+// Both LoG responses of the centre row of the ring (ring row RB).  Orbit
+// (i, j), i >= j, is the set of offsets {(+-i, +-j), (+-j, +-i)}; its pixel
+// sum is assembled from pair sums of the rows centre +- i and centre +- j.
+template <class Acc, int RA, int RB>
+__device__ inline void log_pair(const int (&h)[2 * RB + 1][RB + 1],
+                                const typename AccOps<Acc>::Taps &t, Acc (&out)[2]) {
+    Acc l0 = 0, l1 = 0;
+#pragma unroll
+    for (int i = 0; i <= RB; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            int o;
+            if (i == 0) o = h[RB][0];
+            else if (j == 0) o = h[RB][i] + h[RB - i][0] + h[RB + i][0];
+            else if (i == j) o = h[RB - i][i] + h[RB + i][i];
+            else o = h[RB - i][j] + h[RB + i][j] + h[RB - j][i] + h[RB + j][i];
+            const int idx = orbit_index(i, j);
+            if (i <= RA) l0 = AccOps<Acc>::mac(t.k[0][idx], o, l0);
+            l1 = AccOps<Acc>::mac(t.k[1][idx], o, l1);
+        }
+    }
+    out[0] = l0;
+    out[1] = l1;
+}
+
+// Zero-crossing strength (Sec. 3.2) of centre a with neighbours up, dn, lf,
+// rt; returns the strength if a is a crossing stronger than thr, else 0.
+// For a < 0 the pair (a, q) with q > 0 marks a iff |a| <= |q|, i.e. a + q >= 0
+// (ties go to the negative pixel); for a > 0 it marks a iff a + q < 0.  Taking
+// the largest / smallest neighbour decides "some neighbour" at once.
+template <class Acc>
+__device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, double thr) {
+    const Acc qmax = max(max(up, dn), max(lf, rt));
+    const Acc qmin = min(min(up, dn), min(lf, rt));
+    const bool nz = a < 0 ? (a + qmax >= 0) : (a + qmin < 0);
+    const bool zr = (lf < 0 && rt > 0) || (lf > 0 && rt < 0) || (up < 0 && dn > 0) ||
+                    (up > 0 && dn < 0);
+    const bool is = (a != 0) ? nz : zr;
+    const double c = AccOps<Acc>::range(max(a, qmax), min(a, qmin));
+    return (is && c > thr) ? c : 0.0;
+}
+
+// Lane offset (x4, for ds_bpermute) of the clamped column col.
+__device__ inline int lane_addr(long long col, long long W, long long base) {
+    long long c = clampll(col, 0, W - 1) - base;
+    c = clampll(c, 0, kWave - 1);
+    return (int)c * 4;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---- bit-sliced majority logic for the binary hybrid median ----
+// Bit l of a row mask is the pixel of lane l; sh(e, d) moves column x + d
+// to bit l.
+template <int D>
+__device__ inline uint64_t sh(uint64_t e) {
+    if constexpr (D >= 0) return e >> D;
+    else return e << (-D);
+}
+__device__ inline uint64_t maj3(uint64_t a, uint64_t b, uint64_t c) { return (a & b) | (c & (a | b)); }
+__device__ inline void fadd(uint64_t a, uint64_t b, uint64_t c, uint64_t &s, uint64_t &cy) {
+    const uint64_t t = a ^ b;
+    s = t ^ c;
+    cy = (a & b) | (c & t);
+}
+// At least 5 of 9.
+__device__ inline uint64_t maj9(uint64_t x1, uint64_t x2, uint64_t x3, uint64_t x4, uint64_t x5,
+                                uint64_t x6, uint64_t x7, uint64_t x8, uint64_t x9) {
+    uint64_t s1, c1, s2, c2, s3, c3, s4, c4;
+    fadd(x1, x2, x3, s1, c1);
+    fadd(x4, x5, x6, s2, c2);
+    fadd(x7, x8, x9, s3, c3);
+    fadd(s1, s2, s3, s4, c4);
+    // count = s4 + 2 * (#ones among c1..c4); >= 5 <=> #c >= 3, or #c == 2 and s4.
+    const uint64_t ge2 = (c1 & c2) | (c3 & c4) | ((c1 | c2) & (c3 | c4));
+    const uint64_t ge3 = (c1 & c2 & (c3 | c4)) | (c3 & c4 & (c1 | c2));
+    return ge3 | (ge2 & s4);
+}
+// At least 3 of 5.
+__device__ inline uint64_t maj5(uint64_t x1, uint64_t x2, uint64_t x3, uint64_t x4, uint64_t x5) {
+    uint64_t s1, c1, s2, c2;
+    fadd(x1, x2, x3, s1, c1);
+    fadd(x4, x5, s1, s2, c2);
+    return (c1 & c2) | ((c1 | c2) & s2);
+}
+// Hybrid median (Sec. 3.4) of rows e[0..4] = rows r-2..r+2: median of the
+// "+" subgroup, of the "x" subgroup (centre in both) and the centre.
+__device__ inline uint64_t hmed5(const uint64_t (&e)[5]) {
+    const uint64_t p = maj9(sh<-2>(e[2]), sh<-1>(e[2]), e[2], sh<1>(e[2]), sh<2>(e[2]), e[0], e[1],
+                            e[3], e[4]);
+    const uint64_t x = maj9(sh<-2>(e[0]), sh<-1>(e[1]), e[2], sh<1>(e[3]), sh<2>(e[4]), sh<2>(e[0]),
+                            sh<1>(e[1]), sh<-1>(e[3]), sh<-2>(e[4]));
+    return maj3(p, x, e[2]);
+}
+__device__ inline uint64_t hmed3(const uint64_t (&e)[5]) {
+    const uint64_t p = maj5(sh<-1>(e[2]), e[2], sh<1>(e[2]), e[1], e[3]);
+    const uint64_t x = maj5(sh<-1>(e[1]), sh<1>(e[1]), e[2], sh<-1>(e[3]), sh<1>(e[3]));
+    return maj3(p, x, e[2]);
+}
+// Replicate the bit of the first / last in-image lane into the lanes that
+// lie left / right of the image, so shifted reads see clamped columns.
+__device__ inline uint64_t clamp_bits(uint64_t e, int lo, int hi) {
+    if (lo > 0) {
+        const uint64_t m = (1ull << lo) - 1;
+        e = (e & ~m) | (((e >> lo) & 1ull) ? m : 0ull);
+    }
+    if (hi < kWave - 1) {
+        const uint64_t m = ~((2ull << hi) - 1);
+        e = (e & ~m) | (((e >> hi) & 1ull) ? m : 0ull);
+    }
+    return e;
+}
+
+// ------------------------------------------------------------- pass 1
+template <class Acc, int RA, int RB, bool DBG>
+__global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
+    extern __shared__ uint16_t lds[];
+    __shared__ double red[4][8];
+    __shared__ long long redc[2][8];
+    constexpr int HL = kHalo1, OW = kWave - 2 * HL, P = 2 * RB + 1;
+
+    const int tile = xcd_remap(blockIdx.x, a.ntiles);
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const long long H = a.img.H, W = a.img.W;
+    const int TW = a.waves * OW;
+    const long long x0 = (long long)tx * TW, y0 = (long long)ty * a.rows;
+    const int Rv = (int)min((long long)a.rows, H - y0);
+    const int RW = TW + 2 * HL + 2 * RB, stride = (RW + 1) & ~1;
+    const int RH = Rv + 2 * HL + 2 * RB;
+    load_tile(lds, stride, a.img, y0 - HL - RB, x0 - HL - RB, RH, RW);
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const long long xw = x0 + (long long)wave * OW, base = xw - HL;
+    const long long xc = base + lane;
+    const int lc = wave * OW + lane + RB;
+    const int aL = lane_addr(xc - 1, W, base), aR = lane_addr(xc + 1, W, base);
+    const bool outc = lane >= HL && lane < HL + OW && xc < W;
+
+    int h[P][RB + 1];
+#pragma unroll
+    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * stride + lc, h[s + 1]);
+    Acc La[2] = {0, 0}, Lb[2] = {0, 0}, Lc[2] = {0, 0};
+    double sz[2] = {0.0, 0.0}, sq[2] = {0.0, 0.0};
+    int cnt[2] = {0, 0};
+    const int nsteps = Rv + 2 * HL;
+    const long long t0 = y0 - HL;
+
+    // One step = one new input row.  Full groups of P steps are unrolled so
+    // the register rings rotate by renaming; the last partial group runs
+    // rolled.
+    auto step = [&](const int si) __attribute__((always_inline)) {
+#pragma unroll
+            for (int s = 0; s < P - 1; ++s)
+#pragma unroll
+                for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
+            load_hrow<RB>(lds + (si + 2 * RB) * stride + lc, h[P - 1]);
+            Acc Ln[2];
+            log_pair<Acc, RA, RB>(h, a.taps, Ln);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                La[j] = Lb[j];
+                Lb[j] = Lc[j];
+                Lc[j] = Ln[j];
+            }
+            {   // zero crossings of row t - 1 (valid from the third step on)
+                const long long r = t0 + si - 1;
+                const bool top = r == 0, bot = r == H - 1;
+                const bool use = outc && si >= 2;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const Acc c = Lb[j];
+                    const Acc up = top ? c : La[j];
+                    const Acc dn = bot ? c : Lc[j];
+                    const Acc lf = bperm(aL, c), rt = bperm(aR, c);
+                    const double z = zc_strength<Acc>(c, up, dn, lf, rt, a.zc_thr[j]);
+                    if (use) {
+                        sz[j] += z;
+                        sq[j] = __fma_rn(z, z, sq[j]);
+                        cnt[j] += z != 0.0;
+                        if constexpr (DBG) {
+                            if (a.dbgL[j]) a.dbgL[j][r * W + xc] = AccOps<Acc>::to_d(c) * a.unit[j];
+                            if (a.dbgZ[j]) a.dbgZ[j][r * W + xc] = z * a.unit[j];
+                        }
+                    }
+                }
+            }
+    };
+    int si0 = 0;
+    for (; si0 + P <= nsteps; si0 += P) {
+#pragma unroll
+        for (int ph = 0; ph < P; ++ph) step(si0 + ph);
+    }
+    for (; si0 < nsteps; ++si0) step(si0);
+
+    // Deterministic per-tile reduction: fixed butterfly per wave, then the
+    // waves in order.
+    double v[4] = {wave_sum(sz[0]), wave_sum(sz[1]), wave_sum(sq[0]), wave_sum(sq[1])};
+    int c0 = wave_sum(cnt[0]), c1 = wave_sum(cnt[1]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[k][wave] = v[k];
+        redc[0][wave] = c0;
+        redc[1][wave] = c1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+        double s[4] = {0, 0, 0, 0};
+        long long cc[2] = {0, 0};
+        for (int w = 0; w < nw; ++w) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[k] += red[k][w];
+            cc[0] += redc[0][w];
+            cc[1] += redc[1][w];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.partials[(long long)tile * 4 + k] = s[k];
+        a.counts[(long long)tile * 2 + 0] = cc[0];
+        a.counts[(long long)tile * 2 + 1] = cc[1];
+    }
+}
+
+// ------------------------------------------------------------- finalize
+__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
+    __shared__ double sd[4][256];
+    __shared__ long long sc[2][256];
+    const int t = threadIdx.x;
+    double s[4] = {0, 0, 0, 0};
+    long long c[2] = {0, 0};
+    for (int i = t; i < a.ntiles; i += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += a.partials[(long long)i * 4 + k];
+        c[0] += a.counts[(long long)i * 2];
+        c[1] += a.counts[(long long)i * 2 + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sd[k][t] = s[k];
+    sc[0][t] = c[0];
+    sc[1][t] = c[1];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sd[k][t] += sd[k][t + off];
+            sc[0][t] += sc[0][t + off];
+            sc[1][t] += sc[1][t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double n = (double)a.n;
+        for (int j = 0; j < 2; ++j) {
+            const double S = sd[j][0], Q = sd[2 + j][0];
+            double var = a.n > 1 ? (Q - S * (S / n)) / (n - 1.0) : 0.0;
+            if (!(var > 0.0)) var = 0.0;
+            const double sg = sqrt(var);
+            const double T = a.std_mode == 0 ? a.std_k * sg : a.abs_thr[j];
+            a.stats->sum[j] = S;
+            a.stats->sumsq[j] = Q;
+            a.stats->sigma[j] = sg;
+            a.stats->thresh[j] = T;
+            a.stats->thr72[j] = 72.0 * T * T;
+            a.stats->zc[j] = sc[j][0];
+        }
+    }
+}
+
+// ------------------------------------------------------------- pass 2
+template <class Acc, int RA, int RB>
+__global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
+    extern __shared__ uint16_t lds[];
+    __shared__ int redc[2][8];
+    constexpr int HL = kHalo2, OW = kWave - 2 * HL, P = 2 * RB + 1;
+
+    const int tile = xcd_remap(blockIdx.x, a.ntiles);
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const long long H = a.img.H, W = a.img.W;
+    const int TW = a.waves * OW;
+    const long long x0 = (long long)tx * TW, y0 = (long long)ty * a.rows;
+    const int Rv = (int)min((long long)a.rows, H - y0);
+    const int RW = TW + 2 * HL + 2 * RB, stride = (RW + 1) & ~1;
+    const int RH = Rv + 2 * HL + 2 * RB;
+    load_tile(lds, stride, a.img, y0 - HL - RB, x0 - HL - RB, RH, RW);
+    __syncthreads();
+
+    const double thr72_0 = a.stats->thr72[0], thr72_1 = a.stats->thr72[1];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const long long xw = x0 + (long long)wave * OW, base = xw - HL;
+    const long long xc = base + lane;
+    const int lc = wave * OW + lane + RB;
+    const int aL = lane_addr(xc - 1, W, base), aR = lane_addr(xc + 1, W, base);
+    const bool outc = lane >= HL && lane < HL + OW && xc < W;
+    // lanes of the first / last image column inside this wave (for the
+    // bit-level clamping of the extracted map)
+    const int lo_lane = base < 0 ? (int)(-base) : 0;
+    const int hi_lane = (int)clampll(W - 1 - base, 0, kWave - 1);
+    const uint64_t mybit = 1ull << lane;
+
+    int h[P][RB + 1];
+#pragma unroll
+    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * stride + lc, h[s + 1]);
+    Acc La[2] = {0, 0}, Lb[2] = {0, 0}, Lc[2] = {0, 0};
+    double Za[2] = {0, 0}, Zb[2] = {0, 0}, Zc[2] = {0, 0};
+    uint64_t e[5] = {0, 0, 0, 0, 0};
+    int ecnt = 0, fcnt = 0;
+    const int nsteps = Rv + 2 * HL;
+    const long long t0 = y0 - HL;
+
+    // One step = one new input row.  Full groups of P steps are unrolled so
+    // the register rings rotate by renaming; the last partial group runs
+    // rolled.
+    auto step = [&](const int si) __attribute__((always_inline)) {
+#pragma unroll
+            for (int s = 0; s < P - 1; ++s)
+#pragma unroll
+                for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
+            load_hrow<RB>(lds + (si + 2 * RB) * stride + lc, h[P - 1]);
+            Acc Ln[2];
+            log_pair<Acc, RA, RB>(h, a.taps, Ln);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                La[j] = Lb[j];
+                Lb[j] = Lc[j];
+                Lc[j] = Ln[j];
+            }
+            // The later stages run from the first step on; what they compute
+            // before their inputs are valid is shifted out of the rings before
+            // any output uses it.  Only the output row is guarded.
+            {   // zero-crossing strength of row t - 1
+                const long long r = t0 + si - 1;
+                const bool top = r == 0, bot = r == H - 1;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const Acc c = Lb[j];
+                    const Acc up = top ? c : La[j];
+                    const Acc dn = bot ? c : Lc[j];
+                    const Acc lf = bperm(aL, c), rt = bperm(aR, c);
+                    Za[j] = Zb[j];
+                    Zb[j] = Zc[j];
+                    Zc[j] = zc_strength<Acc>(c, up, dn, lf, rt, a.zc_thr[j]);
+                }
+            }
+            {   // extraction of row t - 2: 3x3 deviation of Z against T
+                const long long r = t0 + si - 2;
+                const bool top = r == 0, bot = r == H - 1;
+                bool ej = false;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const double zu = top ? Zb[j] : Za[j];
+                    const double zd = bot ? Zb[j] : Zc[j];
+                    const double cs = zu + Zb[j] + zd;
+                    const double cq = __fma_rn(zu, zu, __fma_rn(Zb[j], Zb[j], zd * zd));
+                    const double S = bperm(aL, cs) + cs + bperm(aR, cs);
+                    const double Q = bperm(aL, cq) + cq + bperm(aR, cq);
+                    // 9 sum z^2 - (sum z)^2 = 72 s^2 for the unbiased s of eq. (2)
+                    const double V = __fma_rn(-S, S, 9.0 * Q);
+                    ej = ej || (V > (j == 0 ? thr72_0 : thr72_1));
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) e[k] = e[k + 1];
+                e[4] = clamp_bits(__ballot(ej), lo_lane, hi_lane);
+            }
+            if (si >= 8) {   // output row t - 4
+                const long long r = t0 + si - 4;
+                uint64_t w[5];
+#pragma unroll
+                for (int d = -2; d <= 2; ++d) {
+                    const long long rr = clampll(r + d, 0, H - 1);
+                    const int k = (int)(rr - r) + 2;
+                    w[d + 2] = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : k == 3 ? e[3] : e[4];
+                }
+                const uint64_t f = a.smooth ? (a.median_size == 3 ? hmed3(w) : hmed5(w)) : w[2];
+                if (outc) {
+                    const int fb = (f & mybit) != 0;
+                    a.out[r * a.out_pitch + xc] = (uint8_t)fb;
+                    fcnt += fb;
+                    ecnt += (w[2] & mybit) != 0;
+                }
+            }
+    };
+    int si0 = 0;
+    for (; si0 + P <= nsteps; si0 += P) {
+#pragma unroll
+        for (int ph = 0; ph < P; ++ph) step(si0 + ph);
+    }
+    for (; si0 < nsteps; ++si0) step(si0);
+
+    const int c0 = wave_sum(ecnt), c1 = wave_sum(fcnt);
+    if (lane == 0) {
+        redc[0][wave] = c0;
+        redc[1][wave] = c1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s0 = 0, s1 = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+            s0 += redc[0][w];
+            s1 += redc[1][w];
+        }
+        a.counts[(long long)tile * 2] = s0;
+        a.counts[(long long)tile * 2 + 1] = s1;
+    }
+}
+
+// ------------------------------------------------------------- dispatch
+template <class Acc, int RA, int RB, bool DBG>
+hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
+    const size_t shm = lds_bytes(a.waves, a.rows, kHalo1, RB);
+    hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG>), dim3(a.ntiles), dim3(a.waves * kWave), shm,
+                       s, a);
+    return hipGetLastError();
+}
+template <class Acc, int RA, int RB>
+hipError_t p2(const Pass2Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
+    const size_t shm = lds_bytes(a.waves, a.rows, kHalo2, RB);
+    hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB>), dim3(a.ntiles), dim3(a.waves * kWave), shm, s, a);
+    return hipGetLastError();
+}
+
+#define LOGFX_RADII(X)                                                                            \
+    X(1, 1) X(1, 2) X(2, 2) X(1, 3) X(2, 3) X(3, 3) X(1, 4) X(2, 4) X(3, 4) X(4, 4)
+
+template <class Acc>
+hipError_t dispatch1(int ra, int rb, const Pass1Args<typename AccOps<Acc>::Taps> &a, bool dbg,
+                     hipStream_t s) {
+#define X(A, B)                                                                                   \
+    if (ra == A && rb == B) return dbg ? p1<Acc, A, B, true>(a, s) : p1<Acc, A, B, false>(a, s);
+    LOGFX_RADII(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+template <class Acc>
+hipError_t dispatch2(int ra, int rb, const Pass2Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
+#define X(A, B)                                                                                   \
+    if (ra == A && rb == B) return p2<Acc, A, B>(a, s);
+    LOGFX_RADII(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, hipStream_t s) {
+    return dispatch1<int>(ra, rb, a, dbg, s);
+}
+hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, hipStream_t s) {
+    return dispatch1<double>(ra, rb, a, dbg, s);
+}
+hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, hipStream_t s) {
+    return dispatch2<int>(ra, rb, a, s);
+}
+hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, hipStream_t s) {
+    return dispatch2<double>(ra, rb, a, s);
+}
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace logfx

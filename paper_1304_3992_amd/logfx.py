@@ -1,0 +1,257 @@
+"""ctypes binding of liblogfx (include/logfx.h), same names as the C ABI.
+
+Argument marshalling only: every step of the pipeline runs in the HIP
+kernels of ``liblogfx.so``.  torch provides device memory and streams.  The
+binding fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblogfx.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
+U8, U16 = 0, 1
+STD_REL, STD_ABS = 0, 1
+SMOOTH_NEVER, SMOOTH_ALWAYS = 0, 1
+PATH_INT32, PATH_FP64 = 0, 1
+
+EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
+           "logfx_make_log_mask", "logfx_check_params", "logfx_extract", "logfx_extract_maps",
+           "logfx_timing_enable", "logfx_timing_read"]
+
+
+class LogfxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblogfx error {code}: {msg}")
+        self.code = code
+
+
+class logfx_image(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("bits", ctypes.c_int32),
+                ("height", ctypes.c_int64), ("width", ctypes.c_int64), ("pitch", ctypes.c_int64)]
+
+
+class logfx_mask(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("taps", ctypes.POINTER(ctypes.c_float))]
+
+
+class logfx_params(ctypes.Structure):
+    _fields_ = [("mask", logfx_mask * 2), ("zc_thresh", ctypes.c_double),
+                ("std_mode", ctypes.c_int32), ("std_k", ctypes.c_double),
+                ("std5_max", ctypes.c_double), ("smooth", ctypes.c_int32),
+                ("median_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class logfx_report(ctypes.Structure):
+    _fields_ = [("pixels", ctypes.c_int64), ("sigma_g", ctypes.c_double * 2),
+                ("thresh", ctypes.c_double * 2), ("zc_count", ctypes.c_int64 * 2),
+                ("extracted", ctypes.c_int64), ("output", ctypes.c_int64),
+                ("path", ctypes.c_int32), ("smoothed", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"pixels": self.pixels, "sigma_g": list(self.sigma_g), "thresh": list(self.thresh),
+                "zc_count": list(self.zc_count), "extracted": self.extracted,
+                "output": self.output, "path": self.path, "smoothed": self.smoothed}
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load liblogfx.so (torch is imported first so that one HIP runtime
+    serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblogfx.so not built ({path}); run `python -m paper_1304_3992_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.logfx_version.restype = ctypes.c_char_p
+    lib.logfx_version.argtypes = []
+    lib.logfx_create.restype = ctypes.c_int
+    lib.logfx_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.logfx_destroy.restype = ctypes.c_int
+    lib.logfx_destroy.argtypes = [P]
+    lib.logfx_last_error.restype = ctypes.c_char_p
+    lib.logfx_last_error.argtypes = [P]
+    lib.logfx_make_log_mask.restype = ctypes.c_int
+    lib.logfx_make_log_mask.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_double)]
+    lib.logfx_check_params.restype = ctypes.c_int
+    lib.logfx_check_params.argtypes = [ctypes.POINTER(logfx_image), ctypes.POINTER(logfx_params),
+                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.logfx_extract.restype = ctypes.c_int
+    lib.logfx_extract.argtypes = [P, ctypes.POINTER(logfx_image), ctypes.POINTER(logfx_params), P,
+                                  ctypes.POINTER(logfx_report), P]
+    lib.logfx_extract_maps.restype = ctypes.c_int
+    lib.logfx_extract_maps.argtypes = [P, ctypes.POINTER(logfx_image),
+                                       ctypes.POINTER(logfx_params), P, P, P, P, P]
+    lib.logfx_timing_enable.restype = ctypes.c_int
+    lib.logfx_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.logfx_timing_read.restype = ctypes.c_int
+    lib.logfx_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().logfx_version().decode()
+
+
+def last_error(ctx=None) -> str:
+    msg = load().logfx_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def _check(rc, ctx=None):
+    if rc != OK:
+        raise LogfxError(rc, last_error(ctx))
+
+
+def make_log_mask(size: int, sigma: float, grid_bits: int = 16):
+    """logfx_make_log_mask: returns (taps float32 [size, size], unit)."""
+    taps = np.zeros((size, size), np.float32)
+    unit = ctypes.c_double(0.0)
+    lib = load()
+    _check(lib.logfx_make_log_mask(size, sigma, grid_bits,
+                                   taps.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   ctypes.byref(unit)))
+    return taps, unit.value
+
+
+class Params:
+    """Holds a logfx_params struct and keeps its tap arrays alive."""
+
+    def __init__(self, taps1, taps2, *, zc_thresh=0.0, std_mode=STD_REL, std_k=2.0,
+                 std5_max=-1.0, smooth=True, median_size=5, flags=0):
+        self.t1 = np.ascontiguousarray(taps1, dtype=np.float32)
+        self.t2 = np.ascontiguousarray(taps2, dtype=np.float32)
+        p = logfx_params()
+        for i, t in enumerate((self.t1, self.t2)):
+            p.mask[i].size = t.shape[0]
+            p.mask[i].taps = t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        p.zc_thresh = zc_thresh
+        p.std_mode = std_mode
+        p.std_k = std_k
+        p.std5_max = std5_max
+        p.smooth = SMOOTH_ALWAYS if smooth else SMOOTH_NEVER
+        p.median_size = median_size
+        p.flags = flags
+        self.c = p
+
+
+def _torch_dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.uint8:
+        return U8
+    if t.dtype in (torch.int16, torch.uint16):
+        return U16
+    raise TypeError(f"images are uint8 or 16-bit tensors, got {t.dtype}")
+
+
+def image(t, bits: int = 0) -> logfx_image:
+    """Describe a 2-D device tensor (uint8, or int16/uint16 holding 16-bit
+    pixels); the row stride of the tensor is the pitch."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("image must be a 2-D tensor with unit column stride")
+    im = logfx_image()
+    im.data = t.data_ptr()
+    im.dtype = _torch_dtype_code(t)
+    im.bits = bits
+    im.height, im.width = t.shape
+    im.pitch = t.stride(0)
+    return im
+
+
+def check_params(img: logfx_image, params: Params) -> int:
+    path = ctypes.c_int32(-1)
+    _check(load().logfx_check_params(ctypes.byref(img), ctypes.byref(params.c), ctypes.byref(path)))
+    return path.value
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns a logfx_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.ptr = ctypes.c_void_p()
+        _check(self.lib.logfx_create(ctypes.byref(self.ptr), device))
+        self.device = device
+
+    def close(self):
+        if self.ptr:
+            self.lib.logfx_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def extract(self, img_t, params: Params, out=None, *, bits: int = 0, report: bool = False,
+                stream=None):
+        """logfx_extract on a device tensor; returns the uint8 map (and the
+        report dict when ``report``)."""
+        import torch
+        img = image(img_t, bits)
+        if out is None:
+            out = torch.empty(img_t.shape, dtype=torch.uint8, device=img_t.device)
+        rep = logfx_report() if report else None
+        rc = self.lib.logfx_extract(self.ptr, ctypes.byref(img), ctypes.byref(params.c),
+                                    ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.byref(rep) if rep is not None else None,
+                                    _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return (out, rep.as_dict()) if report else out
+
+    def timing_enable(self, on: bool = True):
+        _check(self.lib.logfx_timing_enable(self.ptr, int(bool(on))), self.ptr)
+
+    def timing_read(self):
+        """Summed kernel milliseconds (pass 1, finalize, pass 2) and the
+        number of timed calls since the last read."""
+        ms = (ctypes.c_double * 3)()
+        calls = ctypes.c_int64(0)
+        _check(self.lib.logfx_timing_read(self.ptr, ms, ctypes.byref(calls)), self.ptr)
+        return list(ms), calls.value
+
+    def extract_maps(self, img_t, params: Params, *, bits: int = 0, want=("L1", "L2", "Z1", "Z2"),
+                     stream=None):
+        """logfx_extract_maps: returns a dict of FP64 device maps."""
+        import torch
+        img = image(img_t, bits)
+        outs = {k: torch.empty(img_t.shape, dtype=torch.float64, device=img_t.device)
+                for k in want}
+        ptr = [ctypes.c_void_p(outs[k].data_ptr()) if k in outs else None
+               for k in ("L1", "L2", "Z1", "Z2")]
+        rc = self.lib.logfx_extract_maps(self.ptr, ctypes.byref(img), ctypes.byref(params.c),
+                                         *ptr, _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return outs

@@ -79,12 +79,15 @@ def panchromatic(height: int, width: int, seed: int, *, n_rect: int = 40, n_poly
     H, W = int(height), int(width)
     maxv = (1 << bits) - 1
     theta = rng.uniform(0.0, 2.0 * math.pi)
-    yy, xx = np.mgrid[0:H, 0:W]
-    proj = (xx * math.cos(theta) + yy * math.sin(theta)).astype(np.float64)
-    span = proj.max() - proj.min()
-    t = (proj - proj.min()) / span if span > 0 else np.zeros_like(proj)
-    img = 60.0 + 80.0 * t
-    del yy, xx, proj, t
+    img = np.arange(H, dtype=np.float64)[:, None] * math.sin(theta) + \
+        np.arange(W, dtype=np.float64)[None, :] * math.cos(theta)
+    lo, hi = img.min(), img.max()
+    if hi > lo:
+        img -= lo
+        img *= 80.0 / (hi - lo)
+    else:
+        img[:] = 0.0
+    img += 60.0
     for _ in range(int(n_rect)):
         h = int(rng.integers(8, 65))
         w = int(rng.integers(8, 65))
@@ -97,7 +100,8 @@ def panchromatic(height: int, width: int, seed: int, *, n_rect: int = 40, n_poly
         img *= maxv / 255.0
     if noise_sigma > 0:
         img += rng.normal(0.0, noise_sigma, size=img.shape)
-    img = np.clip(np.rint(img), 0, maxv)
+    np.rint(img, out=img)
+    np.clip(img, 0, maxv, out=img)
     if sp_density > 0:
         u = rng.random(img.shape)
         img[u < sp_density / 2] = 0

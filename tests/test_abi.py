@@ -1,0 +1,152 @@
+"""Host-side checks of liblogfx (no GPU): the library loads, exports every
+symbol include/logfx.h declares, builds the same masks as the oracle, and
+rejects invalid requests before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1304_3992_amd import logfx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "logfx.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(logfx_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(logfx.LIB_PATH):
+        pytest.fail("liblogfx.so is not built; run python -m paper_1304_3992_amd.build")
+    return logfx.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in logfx.h but not exported"
+    assert set(logfx.EXPORTS) == set(names)
+
+
+def test_version(lib):
+    assert "liblogfx" in logfx.version()
+
+
+@pytest.mark.parametrize("size,sigma", [(1, 1.0), (3, 0.5), (5, 0.8), (7, 1.0), (9, 1.4),
+                                        (11, 2.0), (15, 3.0)])
+@pytest.mark.parametrize("bits", [8, 16, 23])
+def test_library_masks_equal_oracle_masks(lib, size, sigma, bits):
+    """Each side builds its masks from eq. (1) on its own; they must agree bit
+    for bit so that both sides run the same problem."""
+    if size == 1:
+        with pytest.raises(Exception):
+            oracle.log_mask(size, sigma, bits)
+        with pytest.raises(logfx.LogfxError):
+            logfx.make_log_mask(size, sigma, bits)
+        return
+    a, ua = oracle.log_mask(size, sigma, bits)
+    b, ub = logfx.make_log_mask(size, sigma, bits)
+    assert ua == ub
+    assert a.tobytes() == b.tobytes()
+
+
+def _img(h=16, w=16, dtype=logfx.U8, bits=0, pitch=None):
+    im = logfx.logfx_image()
+    im.data = 0x1000  # never dereferenced by check_params
+    im.dtype, im.bits, im.height, im.width = dtype, bits, h, w
+    im.pitch = w if pitch is None else pitch
+    return im
+
+
+def _params(s1=5, g1=0.8, s2=9, g2=1.4, bits=16, **kw):
+    return logfx.Params(logfx.make_log_mask(s1, g1, bits)[0], logfx.make_log_mask(s2, g2, bits)[0], **kw)
+
+
+def _rc(img, params):
+    return lib_rc(logfx.load(), img, params)
+
+
+def lib_rc(lib, img, params):
+    path = ctypes.c_int32(-1)
+    rc = lib.logfx_check_params(ctypes.byref(img) if img is not None else None,
+                                ctypes.byref(params.c) if params is not None else None,
+                                ctypes.byref(path))
+    return rc, path.value
+
+
+def test_check_params_paths(lib):
+    # 16-bit-grid masks: exact in int32 for 8- and 11-bit pixels, FP64 beyond
+    assert _rc(_img(), _params()) == (logfx.OK, logfx.PATH_INT32)
+    assert _rc(_img(dtype=logfx.U16, bits=11), _params()) == (logfx.OK, logfx.PATH_INT32)
+    assert _rc(_img(dtype=logfx.U16), _params()) == (logfx.OK, logfx.PATH_FP64)
+    assert _rc(_img(), _params(bits=23)) == (logfx.OK, logfx.PATH_FP64)
+
+
+def test_check_params_rejections(lib):
+    E, U = logfx.EINVAL, logfx.EUNSUPPORTED
+    assert _rc(None, _params())[0] == E
+    assert _rc(_img(h=0), _params())[0] == E
+    assert _rc(_img(w=0), _params())[0] == E
+    assert _rc(_img(pitch=3), _params())[0] == E
+    assert _rc(_img(dtype=7), _params())[0] == E
+    assert _rc(_img(bits=9), _params())[0] == E
+    im = _img()
+    im.data = 0
+    assert _rc(im, _params())[0] == E
+    assert _rc(_img(), _params(std_k=-1.0))[0] == E
+    assert _rc(_img(), _params(zc_thresh=-1.0))[0] == E
+    assert _rc(_img(), _params(zc_thresh=float("nan")))[0] == E
+    assert _rc(_img(), _params(median_size=4))[0] == E
+    assert _rc(_img(), _params(std_mode=3))[0] == E
+    assert _rc(_img(), _params(flags=1))[0] == E
+    assert _rc(_img(), _params(std5_max=2.0))[0] == U
+    p = _params()
+    p.c.smooth = 5
+    assert _rc(_img(), p)[0] == E
+    # mask problems
+    even = logfx.Params(np.zeros((4, 4), np.float32), logfx.make_log_mask(5, 0.8)[0])
+    assert _rc(_img(), even)[0] == E
+    big = logfx.Params(logfx.make_log_mask(11, 2.0)[0], logfx.make_log_mask(5, 0.8)[0])
+    assert _rc(_img(), big)[0] == U
+    asym = logfx.make_log_mask(5, 0.8)[0].copy()
+    asym[0, 1] += asym[0, 1]
+    assert _rc(_img(), logfx.Params(asym, logfx.make_log_mask(9, 1.4)[0]))[0] == U
+    nan = logfx.make_log_mask(5, 0.8)[0].copy()
+    nan[2, 2] = np.nan
+    assert _rc(_img(), logfx.Params(nan, logfx.make_log_mask(9, 1.4)[0]))[0] == E
+    # taps spread over too many binary orders for exact sums with 16-bit pixels
+    wide = np.zeros((3, 3), np.float32)
+    wide[1, 1] = 1.0
+    wide[0, 1] = wide[1, 0] = wide[1, 2] = wide[2, 1] = np.float32(2.0 ** -40)
+    rc = _rc(_img(dtype=logfx.U16), logfx.Params(wide, wide))[0]
+    assert rc == U
+    assert "exact" in logfx.last_error() or "binary orders" in logfx.last_error()
+
+
+def test_mask_builder_rejections(lib):
+    for args in [(4, 1.0, 16), (0, 1.0, 16), (17, 1.0, 16), (5, 0.0, 16), (5, 1.0, 1),
+                 (5, 1.0, 24)]:
+        with pytest.raises(logfx.LogfxError):
+            logfx.make_log_mask(*args)
+
+
+def test_create_without_device_fails_cleanly(lib):
+    """On a machine without a GPU the context call returns an error code
+    instead of aborting."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ptr = ctypes.c_void_p()
+    rc = lib.logfx_create(ctypes.byref(ptr), 0)
+    assert rc in (logfx.EDEVICE, logfx.EINVAL)
+    assert not ptr
+    assert lib.logfx_extract(None, None, None, None, None, None) == logfx.EINVAL
+    assert lib.logfx_destroy(None) == logfx.OK

@@ -1,0 +1,187 @@
+"""GPU parity: liblogfx (through its C ABI) against the CPU oracle on the same
+seeded inputs.  LoG responses and crossing strengths must agree bit for bit
+(both are exact sums); extracted and output maps must agree except where
+the oracle's deviation lies within 1e-5 of its threshold (band pixels), and
+such mismatches must stay below 1e-6 of the pixels."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1304_3992_amd import logfx, scenes
+from parity import compare, masks, run_gpu, run_oracle, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = logfx.Context(0)
+    yield c
+    c.close()
+
+
+def _rand(shape, maxv, seed, dtype):
+    return np.random.default_rng(seed).integers(0, maxv + 1, size=shape).astype(dtype)
+
+
+def _scene_crop(h, w, seed=1, bits=8):
+    if bits == 8:
+        return scenes.panchromatic(h, w, seed, n_rect=max(1, h * w // 6000), noise_sigma=4.0)
+    return scenes.panchromatic(h, w, seed, n_rect=max(1, h * w // 3000), n_poly=3,
+                               noise_sigma=12.0, sp_density=0.05, bits=bits)
+
+
+MAP_CASES = [
+    # (name, image factory, bits, mask pair, grid bits)
+    ("c1crop_u8", lambda: scenes.config1()[:300, :250], 0, ((5, 0.8), (9, 1.4)), 16),
+    ("rand_u8_ragged", lambda: _rand((131, 301), 255, 3, np.uint8), 0, ((5, 0.8), (9, 1.4)), 16),
+    ("scene_u11", lambda: _scene_crop(200, 333, 5, 11), 11, ((5, 0.8), (9, 1.4)), 16),
+    ("rand_u16_fp64", lambda: _rand((97, 150), 65535, 4, np.uint16), 16, ((5, 0.8), (9, 1.4)), 16),
+    ("grid23_fp64", lambda: scenes.config1()[:128, :300], 0, ((5, 0.8), (9, 1.4)), 23),
+    ("swapped_sizes", lambda: _rand((70, 90), 255, 6, np.uint8), 0, ((9, 1.4), (3, 0.5)), 16),
+    ("r1r1", lambda: _rand((65, 129), 255, 7, np.uint8), 0, ((3, 0.5), (3, 0.9)), 16),
+    ("r3r3", lambda: _rand((40, 200), 255, 8, np.uint8), 0, ((7, 1.0), (7, 1.2)), 16),
+    ("r4r4_fp64", lambda: _rand((50, 77), 65535, 9, np.uint16), 16, ((9, 1.4), (9, 2.0)), 16),
+    ("one_pixel", lambda: np.array([[77]], np.uint8), 0, ((5, 0.8), (9, 1.4)), 16),
+    ("one_row", lambda: _rand((1, 200), 255, 10, np.uint8), 0, ((5, 0.8), (9, 1.4)), 16),
+    ("one_col", lambda: _rand((150, 1), 255, 11, np.uint8), 0, ((5, 0.8), (9, 1.4)), 16),
+]
+
+
+@pytest.mark.parametrize("name,make,bits,pair,gb", MAP_CASES, ids=[c[0] for c in MAP_CASES])
+def test_maps_bit_exact(ctx, name, make, bits, pair, gb):
+    import torch
+    img = make()
+    orc_t, lib_t = masks(pair, gb)
+    o = run_oracle(img, orc_t)
+    maps = ctx.extract_maps(to_device(img), logfx.Params(*lib_t), bits=bits)
+    torch.cuda.synchronize()
+    for k in ("L1", "L2", "Z1", "Z2"):
+        g = maps[k].cpu().numpy()
+        ref = o[k]
+        # the 1e-5 relative bound holds trivially; exact equality is the real bar
+        assert np.array_equal(g, ref), (k, int((g != ref).sum()))
+
+
+EXTRACT_CASES = [
+    ("c1", lambda: scenes.config1(), 0, {}),
+    ("c1_nosmooth", lambda: scenes.config1(), 0, dict(smooth=False)),
+    ("c1_med3", lambda: scenes.config1(), 0, dict(median_size=3)),
+    ("c1_abs", lambda: scenes.config1(), 0, dict(std_mode=logfx.STD_ABS, std_k=6.0)),
+    ("c1_zcthr", lambda: scenes.config1(), 0, dict(zc_thresh=2.0)),
+    ("ragged_u8", lambda: _scene_crop(700, 333, 12), 0, {}),
+    ("ragged_u11", lambda: _scene_crop(257, 449, 13, 11), 11, {}),
+    ("u16_fp64", lambda: _scene_crop(190, 230, 14, 16), 16, {}),
+    ("tiny_2x2", lambda: _rand((2, 2), 255, 15, np.uint8), 0, {}),
+    ("tiny_1x1", lambda: np.array([[9]], np.uint8), 0, {}),
+    ("row_1x300", lambda: _rand((1, 300), 255, 16, np.uint8), 0, {}),
+    ("col_300x1", lambda: _rand((300, 1), 255, 17, np.uint8), 0, {}),
+    ("thin_3x500", lambda: _rand((3, 500), 255, 18, np.uint8), 0, dict(median_size=3)),
+    ("checker", lambda: (np.indices((64, 96)).sum(0) % 2 * 200).astype(np.uint8), 0, {}),
+    ("saturated", lambda: (np.random.default_rng(19).random((120, 140)) < 0.5).astype(np.uint16)
+     * 65535, 16, {}),
+    ("constant", lambda: np.full((100, 100), 33, np.uint8), 0, {}),
+]
+
+
+@pytest.mark.parametrize("name,make,bits,kw", EXTRACT_CASES, ids=[c[0] for c in EXTRACT_CASES])
+def test_extract_parity(ctx, name, make, bits, kw):
+    img = make()
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t, **kw)
+    F, rep = run_gpu(ctx, img, lib_t, bits=bits, **kw)
+    compare(F, o, smooth=kw.get("smooth", True), median_size=kw.get("median_size", 5))
+    # the report: exact counts and the global statistics of eq. (2)
+    assert rep["pixels"] == img.size
+    assert rep["zc_count"] == [int((o["Z1"] != 0).sum()), int((o["Z2"] != 0).sum())]
+    assert rep["output"] == int(F.sum())
+    np.testing.assert_allclose(rep["sigma_g"], o["stats"][:2], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(rep["thresh"], o["stats"][2:], rtol=1e-12, atol=0)
+    if name == "constant":
+        assert not F.any() and rep["sigma_g"] == [0.0, 0.0]
+
+
+def test_step_edge_band(ctx):
+    """Worked example: a vertical step gives exactly the three columns around
+    it (see the oracle pins); the GPU must reproduce it."""
+    H, W, c = 32, 64, 20
+    img = np.full((H, W), 40, np.uint8)
+    img[:, c:] = 200
+    _, lib_t = masks()
+    F, _ = run_gpu(ctx, img, lib_t)
+    expect = np.zeros((H, W), np.uint8)
+    expect[:, c - 1:c + 2] = 1
+    assert np.array_equal(F, expect)
+
+
+def test_pitch_larger_than_width(ctx):
+    img = _scene_crop(150, 210, 20)
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t)
+    F, _ = run_gpu(ctx, img, lib_t, pitch=333)
+    compare(F, o, smooth=True)
+
+
+def test_repeatable_and_tile_independent(ctx):
+    """Two runs give identical bytes, and so does a context with another tile
+    shape (tiles change the reduction order of the global sums only)."""
+    img = _scene_crop(600, 500, 21)
+    _, lib_t = masks()
+    a, ra = run_gpu(ctx, img, lib_t)
+    b, rb = run_gpu(ctx, img, lib_t)
+    assert np.array_equal(a, b) and ra == rb
+    old = os.environ.get("LOGFX_TILE")
+    os.environ["LOGFX_TILE"] = "2,24,3,40"
+    try:
+        c2 = logfx.Context(0)
+    finally:
+        if old is None:
+            del os.environ["LOGFX_TILE"]
+        else:
+            os.environ["LOGFX_TILE"] = old
+    c, rc = run_gpu(c2, img, lib_t)
+    c2.close()
+    assert np.array_equal(a, c)
+    assert rc["zc_count"] == ra["zc_count"] and rc["output"] == ra["output"]
+
+
+def test_side_stream(ctx):
+    import torch
+    img = scenes.config1(seed=22)
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t)
+    s = torch.cuda.Stream()
+    t = to_device(img)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out = ctx.extract(t, logfx.Params(*lib_t), stream=s)
+    s.synchronize()
+    compare(out.cpu().numpy(), o, smooth=True)
+
+
+def test_config2_full_size(ctx):
+    """8192^2 11-bit scene with 20000 rectangles, 500 polylines, noise sigma
+    12 and 5 % impulses, at the launch configuration the benchmark uses: the
+    whole output map against the oracle, and the LoG / strength maps on a
+    band of rows."""
+    import torch
+    img = scenes.config2()
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t)
+    F, rep = run_gpu(ctx, img, lib_t, bits=11)
+    info = compare(F, o, smooth=True)
+    assert rep["path"] == logfx.PATH_INT32
+    np.testing.assert_allclose(rep["sigma_g"], o["stats"][:2], rtol=1e-12)
+    maps = ctx.extract_maps(to_device(img), logfx.Params(*lib_t), bits=11)
+    torch.cuda.synchronize()
+    for k in ("L1", "L2", "Z1", "Z2"):
+        g = maps[k]
+        for r0 in (0, 4093, 8192 - 70):
+            assert np.array_equal(g[r0:r0 + 70].cpu().numpy(), o[k][r0:r0 + 70]), (k, r0)
+    del maps
+    print("config2", info)
