@@ -24,19 +24,20 @@ namespace {
 
 thread_local std::string g_thread_error;
 
+// Output rows per wave strip of each pass (tiles are kTileWaves strips wide).
 struct TileCfg {
-    int waves1 = 4, rows1 = 64;  // pass 1
-    int waves2 = 4, rows2 = 64;  // pass 2
+    int rows1 = 64;  // pass 1
+    int rows2 = 64;  // pass 2
 };
 
+// LOGFX_TILE="rows1,rows2" overrides the defaults (used by the tuner and
+// the tests).
 TileCfg tile_cfg_from_env() {
     TileCfg t;
     if (const char *s = std::getenv("LOGFX_TILE")) {
-        int a, b, c, d;
-        if (std::sscanf(s, "%d,%d,%d,%d", &a, &b, &c, &d) == 4 && a >= 1 && a <= 4 && b >= 1 &&
-            c >= 1 && c <= 4 && d >= 1) {
-            t.waves1 = a, t.rows1 = b, t.waves2 = c, t.rows2 = d;
-        }
+        int a, b;
+        if (std::sscanf(s, "%d,%d", &a, &b) == 2 && a >= 1 && a <= 1024 && b >= 1 && b <= 1024)
+            t.rows1 = a, t.rows2 = b;
     }
     return t;
 }
@@ -297,14 +298,15 @@ struct Geometry {
 int geometry(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, Geometry &g) {
     const TileCfg &t = ctx->tiles;
     const long long H = img->height, W = img->width;
-    const long long tw1 = (long long)t.waves1 * (kWave - 2 * kHalo1);
-    const long long tw2 = (long long)t.waves2 * (kWave - 2 * kHalo2);
+    if (H >= (1LL << 30) || W >= (1LL << 30))
+        return set_err(ctx, LOGFX_EUNSUPPORTED, "image sides must be below 2^30");
+    const long long tw1 = (long long)kTileWaves * (kWave - 2 * kHalo1);
+    const long long tw2 = (long long)kTileWaves * (kWave - 2 * kHalo2);
     const long long tx1 = (W + tw1 - 1) / tw1, ty1 = (H + t.rows1 - 1) / t.rows1;
     const long long tx2 = (W + tw2 - 1) / tw2, ty2 = (H + t.rows2 - 1) / t.rows2;
     if (tx1 * ty1 > 0x7fffffffLL || tx2 * ty2 > 0x7fffffffLL)
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image too large for one launch");
-    if (lds_bytes(t.waves1, t.rows1, kHalo1, pl.rb) > 65536 ||
-        lds_bytes(t.waves2, t.rows2, kHalo2, pl.rb) > 65536)
+    if (lds_bytes(t.rows1, kHalo1, pl.rb) > 65536 || lds_bytes(t.rows2, kHalo2, pl.rb) > 65536)
         return set_err(ctx, LOGFX_EUNSUPPORTED, "tile configuration exceeds 64 KiB of LDS");
     g.tiles_x1 = (int)tx1, g.ntiles1 = (int)(tx1 * ty1);
     g.tiles_x2 = (int)tx2, g.ntiles2 = (int)(tx2 * ty2);
@@ -318,6 +320,9 @@ ImageDesc image_desc(const logfx_image *img) {
     d.W = img->width;
     d.pitch = img->pitch;
     d.dtype = img->dtype;
+    // 8 pixels per load need the row starts 8-pixel aligned in bytes
+    const size_t esz = img->dtype == LOGFX_U16 ? 2 : 1;
+    d.vec = ((uintptr_t)img->data % (8 * esz) == 0) && (img->pitch % 8 == 0);
     return d;
 }
 
@@ -338,7 +343,6 @@ hipError_t launch_p1(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const lo
         dbg = dbg || a.dbgL[slot] || a.dbgZ[slot];
     }
     a.rows = ctx->tiles.rows1;
-    a.waves = ctx->tiles.waves1;
     a.tiles_x = g.tiles_x1;
     a.ntiles = g.ntiles1;
     a.partials = ctx->partials;
@@ -356,7 +360,6 @@ hipError_t launch_p2(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const lo
     fill_taps<Taps, V>(pl, a.taps);
     for (int slot = 0; slot < 2; ++slot) a.zc_thr[slot] = p->zc_thresh / pl.mi[pl.order[slot]].unit;
     a.rows = ctx->tiles.rows2;
-    a.waves = ctx->tiles.waves2;
     a.tiles_x = g.tiles_x2;
     a.ntiles = g.ntiles2;
     a.stats = ctx->stats;

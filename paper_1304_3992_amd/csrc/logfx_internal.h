@@ -8,6 +8,7 @@
 namespace logfx {
 
 constexpr int kWave = 64;
+constexpr int kTileWaves = 4;                        // waves (column strips) per workgroup
 constexpr int kMaxRadius = 4;                        // masks up to 9 x 9
 constexpr int kMaxOrbits = (kMaxRadius + 1) * (kMaxRadius + 2) / 2;
 
@@ -39,7 +40,17 @@ struct ImageDesc {
     const void *data;
     long long H, W, pitch;
     int dtype;   // 0 u8, 1 u16
+    int vec;     // rows may be read 8 pixels at a time (data and pitch 8-pixel aligned)
 };
+
+// LDS tile geometry of a pass with halo HL and mask radius rb.  The staged
+// columns start 8-aligned in the image (tiles are 8-multiples wide) so that
+// interior rows are copied 8 pixels per load.
+__host__ __device__ constexpr int tile_out_width(int halo) { return kTileWaves * (kWave - 2 * halo); }
+__host__ __device__ constexpr int tile_lds_offset(int halo, int rb) { return (8 - (halo + rb) % 8) % 8; }
+__host__ __device__ constexpr int tile_lds_stride(int halo, int rb) {
+    return (tile_out_width(halo) + 2 * halo + 2 * rb + tile_lds_offset(halo, rb) + 7) / 8 * 8;
+}
 
 template <class Taps>
 struct Pass1Args {
@@ -47,8 +58,7 @@ struct Pass1Args {
     Taps taps;
     double zc_thr[2];      // zero-crossing threshold per mask, grid units
     int rows;              // output rows per wave strip
-    int waves;             // waves per workgroup (tile width = waves * (64 - 2 halo))
-    int tiles_x;           // tiles across the image
+    int tiles_x;           // tiles across the image (tile width = kTileWaves * (64 - 2 halo))
     int ntiles;            // tiles in the image (= grid size)
     double *partials;      // [ntiles][4]: sum Z1, sum Z2, sum Z1^2, sum Z2^2
     long long *counts;     // [ntiles][2]: crossings of mask 1, mask 2
@@ -64,7 +74,6 @@ struct Pass2Args {
     Taps taps;
     double zc_thr[2];
     int rows;
-    int waves;
     int tiles_x;
     int ntiles;
     const DevStats *stats;  // thresholds from the finalize kernel
@@ -95,11 +104,8 @@ hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, hipStr
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
 // LDS bytes of one workgroup.
-inline size_t lds_bytes(int waves, int rows, int halo, int rb) {
-    const int width = waves * (kWave - 2 * halo) + 2 * halo + 2 * rb;
-    const int height = rows + 2 * halo + 2 * rb;
-    const int stride = (width + 1) & ~1;
-    return (size_t)stride * height * sizeof(uint16_t);
+inline size_t lds_bytes(int rows, int halo, int rb) {
+    return (size_t)tile_lds_stride(halo, rb) * (rows + 2 * halo + 2 * rb) * sizeof(uint16_t);
 }
 
 }  // namespace logfx

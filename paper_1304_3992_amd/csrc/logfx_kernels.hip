@@ -8,7 +8,7 @@
 // work runs as   pass 1 (LoG, Z, per-tile sums) -> finalize (T_j) ->
 // pass 2 (LoG and Z again with a wider halo, local deviation, OR, median).
 //
-// Work decomposition.  A workgroup owns an output tile of `waves` wave-wide
+// Work decomposition.  A workgroup owns an output tile of kTileWaves wave-wide
 // column strips side by side, `rows` rows tall; the input tile plus halo is
 // staged once in LDS as u16 with clamp-to-edge coordinates.  Each lane owns
 // one column and walks down the rows, keeping a ring of 2R+1 rows of
@@ -23,6 +23,8 @@
 // exact (int32 when sum|k| (2^bits - 1) < 2^30, else FP64 below 2^52), so L
 // and Z agree bit for bit with any exact evaluation.
 #include "logfx_internal.h"
+
+#include <type_traits>
 
 namespace logfx {
 namespace {
@@ -42,28 +44,6 @@ __device__ inline long long clampll(long long v, long long lo, long long hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
-template <class T>
-__device__ inline void load_rows(uint16_t *lds, int stride, const T *img, long long pitch,
-                                 long long H, long long W, long long ry0, long long rx0, int RH,
-                                 int RW) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    for (int r = wave; r < RH; r += nw) {
-        const T *src = img + clampll(ry0 + r, 0, H - 1) * pitch;
-        uint16_t *dst = lds + r * stride;
-        for (int c = lane; c < RW; c += kWave) dst[c] = (uint16_t)src[clampll(rx0 + c, 0, W - 1)];
-    }
-}
-
-__device__ inline void load_tile(uint16_t *lds, int stride, const ImageDesc &img, long long ry0,
-                                 long long rx0, int RH, int RW) {
-    if (img.dtype == 0)
-        load_rows(lds, stride, (const uint8_t *)img.data, img.pitch, img.H, img.W, ry0, rx0, RH, RW);
-    else
-        load_rows(lds, stride, (const uint16_t *)img.data, img.pitch, img.H, img.W, ry0, rx0, RH,
-                  RW);
-}
-
 __device__ inline int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
 __device__ inline double bperm(int addr, double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
@@ -74,7 +54,14 @@ __device__ inline double bperm(int addr, double v) {
 template <class Acc> struct AccOps;
 template <> struct AccOps<int> {
     using Taps = OrbitTapsI;
-    static __device__ int mac(int k, int o, int acc) { return acc + __mul24(k, o); }
+    // v_mad_i32_i24 on the raw tap register: both operands fit 24-bit signed
+    // (|k| < 2^23 is checked on the host, o < 2^20), so no sign-extended
+    // copies of the taps need to be kept alive.
+    static __device__ int mac(int k, int o, int acc) {
+        int r;
+        asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "s"(k), "v"(o), "v"(acc));
+        return r;
+    }
     static __device__ double range(int mx, int mn) { return (double)(mx - mn); }
     static __device__ double to_d(int v) { return (double)v; }
 };
@@ -137,10 +124,9 @@ __device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, doub
 }
 
 // Lane offset (x4, for ds_bpermute) of the clamped column col.
-__device__ inline int lane_addr(long long col, long long W, long long base) {
-    long long c = clampll(col, 0, W - 1) - base;
-    c = clampll(c, 0, kWave - 1);
-    return (int)c * 4;
+__device__ inline int lane_addr(int col, int W, int base) {
+    const int c = min(max(col, 0), W - 1) - base;
+    return min(max(c, 0), kWave - 1) * 4;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -216,93 +202,190 @@ __device__ inline uint64_t clamp_bits(uint64_t e, int lo, int hi) {
     return e;
 }
 
+// ------------------------------------------------------------- strips
+// Geometry shared by both passes.  A workgroup owns a tile of kTileWaves strips
+// side by side; each wave's 64 lanes cover image columns base .. base+63,
+// of which lanes HL .. 63-HL are output columns.  Everything but the lane's
+// own column is wave-uniform and lives in scalar registers.
+template <int HL, int RB>
+struct Strip {
+    static constexpr int OW = kWave - 2 * HL;
+    static constexpr int TW = tile_out_width(HL);         // output columns per tile
+    static constexpr int OFF = tile_lds_offset(HL, RB);   // LDS column of image column x0-HL-RB
+    static constexpr int stride = tile_lds_stride(HL, RB);  // LDS row pitch (u16), 8-multiple
+    int H, W, x0, y0, Rv, RH;
+    int lane, base, xc, lc, aL, aR;
+    bool outc;
+
+    __device__ Strip(const ImageDesc &img, int tile, int tiles_x, int rows) {
+        H = (int)img.H;
+        W = (int)img.W;
+        const int tx = tile % tiles_x, ty = tile / tiles_x;
+        x0 = tx * TW;
+        y0 = ty * rows;
+        Rv = min(rows, H - y0);
+        RH = Rv + 2 * HL + 2 * RB;
+        lane = threadIdx.x & (kWave - 1);
+        // the wave index is uniform across the wave: keep it (and all that
+        // derives from it) in scalar registers
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        base = x0 + wave * OW - HL;
+        xc = base + lane;
+        lc = wave * OW + lane + RB + OFF;
+        aL = lane_addr(xc - 1, W, base);
+        aR = lane_addr(xc + 1, W, base);
+        outc = lane >= HL && lane < HL + OW && xc < W;
+    }
+
+    // Stage the input rows y0-HL-RB .. (RH rows) and columns from the
+    // 8-aligned origin x0-HL-RB-OFF (stride columns) in LDS as u16, with
+    // clamp-to-edge coordinates.  Tiles whose columns lie inside the image
+    // copy 8 pixels per load, 8 loads in flight per thread.
+    __device__ void fill(uint16_t *lds, const ImageDesc &img) const {
+        constexpr int CPR = stride / 8;
+        const int ry0 = y0 - HL - RB, rx0 = x0 - HL - RB - OFF;
+        const int nch = RH * CPR;
+        const int nt = blockDim.x;
+        const long long pitch = img.pitch;
+        if (img.vec && rx0 >= 0 && rx0 + stride <= W) {
+            for (int b = 0; b < nch; b += 8 * nt) {
+                uint4 v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = b + k * nt + (int)threadIdx.x;
+                    if (i < nch) {
+                        const int row = i / CPR, ch = i - row * CPR;
+                        const long long at = (long long)min(max(ry0 + row, 0), H - 1) * pitch + rx0 + 8 * ch;
+                        if (img.dtype == 1) {
+                            v[k] = *(const uint4 *)((const uint16_t *)img.data + at);
+                        } else {
+                            const uint2 q = *(const uint2 *)((const uint8_t *)img.data + at);
+                            v[k].x = __builtin_amdgcn_perm(0u, q.x, 0x0c010c00u);
+                            v[k].y = __builtin_amdgcn_perm(0u, q.x, 0x0c030c02u);
+                            v[k].z = __builtin_amdgcn_perm(0u, q.y, 0x0c010c00u);
+                            v[k].w = __builtin_amdgcn_perm(0u, q.y, 0x0c030c02u);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = b + k * nt + (int)threadIdx.x;
+                    if (i < nch) {
+                        const int row = i / CPR, ch = i - row * CPR;
+                        *(uint4 *)(lds + row * stride + 8 * ch) = v[k];
+                    }
+                }
+            }
+        } else {
+            const int w = threadIdx.x / kWave, nw = nt / kWave;
+            for (int r = w; r < RH; r += nw) {
+                const long long row = (long long)min(max(ry0 + r, 0), H - 1) * pitch;
+                uint16_t *dst = lds + r * stride;
+                for (int c = lane; c < stride; c += kWave) {
+                    const long long at = row + min(max(rx0 + c, 0), W - 1);
+                    dst[c] = img.dtype == 1 ? ((const uint16_t *)img.data)[at]
+                                            : (uint16_t)((const uint8_t *)img.data)[at];
+                }
+            }
+        }
+    }
+};
+
+// Row rings keep clamp-to-edge rows: a row past the bottom of the image
+// repeats the last image row, and when row 0 arrives it is copied over the
+// rows above it.  Every stage can then read its ring without border tests.
+// Strips that stay clear of the top and bottom rows skip the tests (CLAMP
+// false).
+template <bool CLAMP, class T, int N>
+__device__ inline void ring_push(T (&ring)[N], T v, int row, int H) {
+    if (CLAMP && row > H - 1) v = ring[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) ring[k] = ring[k + 1];
+    ring[N - 1] = v;
+    if (CLAMP && row == 0) {
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) ring[k] = v;
+    }
+}
+
+template <bool B> using bool_c = std::integral_constant<bool, B>;
+
 // ------------------------------------------------------------- pass 1
 template <class Acc, int RA, int RB, bool DBG>
 __global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ double red[4][8];
     __shared__ long long redc[2][8];
-    constexpr int HL = kHalo1, OW = kWave - 2 * HL, P = 2 * RB + 1;
+    constexpr int HL = kHalo1, P = 2 * RB + 1;
 
     const int tile = xcd_remap(blockIdx.x, a.ntiles);
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const long long H = a.img.H, W = a.img.W;
-    const int TW = a.waves * OW;
-    const long long x0 = (long long)tx * TW, y0 = (long long)ty * a.rows;
-    const int Rv = (int)min((long long)a.rows, H - y0);
-    const int RW = TW + 2 * HL + 2 * RB, stride = (RW + 1) & ~1;
-    const int RH = Rv + 2 * HL + 2 * RB;
-    load_tile(lds, stride, a.img, y0 - HL - RB, x0 - HL - RB, RH, RW);
+    const Strip<HL, RB> g(a.img, tile, a.tiles_x, a.rows);
+    g.fill(lds, a.img);
     __syncthreads();
-
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const long long xw = x0 + (long long)wave * OW, base = xw - HL;
-    const long long xc = base + lane;
-    const int lc = wave * OW + lane + RB;
-    const int aL = lane_addr(xc - 1, W, base), aR = lane_addr(xc + 1, W, base);
-    const bool outc = lane >= HL && lane < HL + OW && xc < W;
 
     int h[P][RB + 1];
 #pragma unroll
-    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * stride + lc, h[s + 1]);
-    Acc La[2] = {0, 0}, Lb[2] = {0, 0}, Lc[2] = {0, 0};
+    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * g.stride + g.lc, h[s + 1]);
+    Acc L[2][3] = {{0, 0, 0}, {0, 0, 0}};   // rows t-2, t-1, t per mask
     double sz[2] = {0.0, 0.0}, sq[2] = {0.0, 0.0};
     int cnt[2] = {0, 0};
-    const int nsteps = Rv + 2 * HL;
-    const long long t0 = y0 - HL;
+    const int nsteps = g.Rv + 2 * HL;
+    const int t0 = g.y0 - HL;
+    const uint16_t *lrow = lds + (2 * RB) * g.stride + g.lc;   // LDS row of step si
 
     // One step = one new input row.  Full groups of P steps are unrolled so
     // the register rings rotate by renaming; the last partial group runs
     // rolled.
-    auto step = [&](const int si) __attribute__((always_inline)) {
+    auto step = [&](const int si, auto clamp) __attribute__((always_inline)) {
+        constexpr bool C = decltype(clamp)::value;
 #pragma unroll
-            for (int s = 0; s < P - 1; ++s)
+        for (int s = 0; s < P - 1; ++s)
 #pragma unroll
-                for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
-            load_hrow<RB>(lds + (si + 2 * RB) * stride + lc, h[P - 1]);
-            Acc Ln[2];
-            log_pair<Acc, RA, RB>(h, a.taps, Ln);
+            for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
+        load_hrow<RB>(lrow, h[P - 1]);
+        lrow += g.stride;
+        const int t = t0 + si;
+        Acc Ln[2];
+        log_pair<Acc, RA, RB>(h, a.taps, Ln);
+        ring_push<C>(L[0], Ln[0], t, g.H);
+        ring_push<C>(L[1], Ln[1], t, g.H);
+        // zero crossings of row t - 1 (valid from the third step on)
+        const int r = t - 1;
+        const bool use = g.outc && si >= 2;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                La[j] = Lb[j];
-                Lb[j] = Lc[j];
-                Lc[j] = Ln[j];
-            }
-            {   // zero crossings of row t - 1 (valid from the third step on)
-                const long long r = t0 + si - 1;
-                const bool top = r == 0, bot = r == H - 1;
-                const bool use = outc && si >= 2;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const Acc c = Lb[j];
-                    const Acc up = top ? c : La[j];
-                    const Acc dn = bot ? c : Lc[j];
-                    const Acc lf = bperm(aL, c), rt = bperm(aR, c);
-                    const double z = zc_strength<Acc>(c, up, dn, lf, rt, a.zc_thr[j]);
-                    if (use) {
-                        sz[j] += z;
-                        sq[j] = __fma_rn(z, z, sq[j]);
-                        cnt[j] += z != 0.0;
-                        if constexpr (DBG) {
-                            if (a.dbgL[j]) a.dbgL[j][r * W + xc] = AccOps<Acc>::to_d(c) * a.unit[j];
-                            if (a.dbgZ[j]) a.dbgZ[j][r * W + xc] = z * a.unit[j];
-                        }
-                    }
+        for (int j = 0; j < 2; ++j) {
+            const Acc c = L[j][1];
+            const Acc lf = bperm(g.aL, c), rt = bperm(g.aR, c);
+            const double z = zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, a.zc_thr[j]);
+            if (use) {
+                sz[j] += z;
+                sq[j] = __fma_rn(z, z, sq[j]);
+                cnt[j] += z != 0.0;
+                if constexpr (DBG) {
+                    const long long at = (long long)r * g.W + g.xc;
+                    if (a.dbgL[j]) a.dbgL[j][at] = AccOps<Acc>::to_d(c) * a.unit[j];
+                    if (a.dbgZ[j]) a.dbgZ[j][at] = z * a.unit[j];
                 }
             }
+        }
     };
-    int si0 = 0;
-    for (; si0 + P <= nsteps; si0 += P) {
+    auto run = [&](auto clamp) __attribute__((always_inline)) {
+        int si0 = 0;
+        for (; si0 + P <= nsteps; si0 += P) {
 #pragma unroll
-        for (int ph = 0; ph < P; ++ph) step(si0 + ph);
-    }
-    for (; si0 < nsteps; ++si0) step(si0);
+            for (int ph = 0; ph < P; ++ph) step(si0 + ph, clamp);
+        }
+        for (; si0 < nsteps; ++si0) step(si0, clamp);
+    };
+    if (t0 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
+    else run(bool_c<true>{});
 
     // Deterministic per-tile reduction: fixed butterfly per wave, then the
     // waves in order.
+    const int wave = threadIdx.x / kWave;
     double v[4] = {wave_sum(sz[0]), wave_sum(sz[1]), wave_sum(sq[0]), wave_sum(sq[1])};
     int c0 = wave_sum(cnt[0]), c1 = wave_sum(cnt[1]);
-    if (lane == 0) {
+    if (g.lane == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) red[k][wave] = v[k];
         redc[0][wave] = c0;
@@ -372,127 +455,104 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
 }
 
 // ------------------------------------------------------------- pass 2
-template <class Acc, int RA, int RB>
+// MED: 0 = no smoothing (output E), 3 or 5 = hybrid median window.
+template <class Acc, int RA, int RB, int MED>
 __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ int redc[2][8];
-    constexpr int HL = kHalo2, OW = kWave - 2 * HL, P = 2 * RB + 1;
+    constexpr int HL = kHalo2, P = 2 * RB + 1;
 
     const int tile = xcd_remap(blockIdx.x, a.ntiles);
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const long long H = a.img.H, W = a.img.W;
-    const int TW = a.waves * OW;
-    const long long x0 = (long long)tx * TW, y0 = (long long)ty * a.rows;
-    const int Rv = (int)min((long long)a.rows, H - y0);
-    const int RW = TW + 2 * HL + 2 * RB, stride = (RW + 1) & ~1;
-    const int RH = Rv + 2 * HL + 2 * RB;
-    load_tile(lds, stride, a.img, y0 - HL - RB, x0 - HL - RB, RH, RW);
+    const Strip<HL, RB> g(a.img, tile, a.tiles_x, a.rows);
+    g.fill(lds, a.img);
     __syncthreads();
 
     const double thr72_0 = a.stats->thr72[0], thr72_1 = a.stats->thr72[1];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const long long xw = x0 + (long long)wave * OW, base = xw - HL;
-    const long long xc = base + lane;
-    const int lc = wave * OW + lane + RB;
-    const int aL = lane_addr(xc - 1, W, base), aR = lane_addr(xc + 1, W, base);
-    const bool outc = lane >= HL && lane < HL + OW && xc < W;
     // lanes of the first / last image column inside this wave (for the
     // bit-level clamping of the extracted map)
-    const int lo_lane = base < 0 ? (int)(-base) : 0;
-    const int hi_lane = (int)clampll(W - 1 - base, 0, kWave - 1);
-    const uint64_t mybit = 1ull << lane;
+    const int lo_lane = g.base < 0 ? -g.base : 0;
+    const int hi_lane = min(max(g.W - 1 - g.base, 0), kWave - 1);
+    const uint64_t mybit = 1ull << g.lane;
 
     int h[P][RB + 1];
 #pragma unroll
-    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * stride + lc, h[s + 1]);
-    Acc La[2] = {0, 0}, Lb[2] = {0, 0}, Lc[2] = {0, 0};
-    double Za[2] = {0, 0}, Zb[2] = {0, 0}, Zc[2] = {0, 0};
-    uint64_t e[5] = {0, 0, 0, 0, 0};
+    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * g.stride + g.lc, h[s + 1]);
+    Acc L[2][3] = {{0, 0, 0}, {0, 0, 0}};        // rows t-2, t-1, t
+    double Z[2][3] = {{0, 0, 0}, {0, 0, 0}};     // rows t-3, t-2, t-1
+    uint64_t e[5] = {0, 0, 0, 0, 0};             // rows t-6 .. t-2
     int ecnt = 0, fcnt = 0;
-    const int nsteps = Rv + 2 * HL;
-    const long long t0 = y0 - HL;
+    const int nsteps = g.Rv + 2 * HL;
+    const int t0 = g.y0 - HL;
+    // output row t - 4 of step si; advanced by one row per step.  The pitch
+    // is moved to a vector register so the per-step offsets are not
+    // materialised as scalar constants.
+    uint8_t *orow = a.out + (long long)(t0 - 4) * a.out_pitch + g.xc;
+    long long opitch;
+    asm("v_mov_b64 %0, %1" : "=v"(opitch) : "s"(a.out_pitch));
+    const uint16_t *lrow = lds + (2 * RB) * g.stride + g.lc;   // LDS row of step si
 
-    // One step = one new input row.  Full groups of P steps are unrolled so
-    // the register rings rotate by renaming; the last partial group runs
-    // rolled.
-    auto step = [&](const int si) __attribute__((always_inline)) {
+    auto step = [&](const int si, auto clamp) __attribute__((always_inline)) {
+        constexpr bool C = decltype(clamp)::value;
 #pragma unroll
-            for (int s = 0; s < P - 1; ++s)
+        for (int s = 0; s < P - 1; ++s)
 #pragma unroll
-                for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
-            load_hrow<RB>(lds + (si + 2 * RB) * stride + lc, h[P - 1]);
-            Acc Ln[2];
-            log_pair<Acc, RA, RB>(h, a.taps, Ln);
+            for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
+        load_hrow<RB>(lrow, h[P - 1]);
+        lrow += g.stride;
+        const int t = t0 + si;
+        Acc Ln[2];
+        log_pair<Acc, RA, RB>(h, a.taps, Ln);
+        ring_push<C>(L[0], Ln[0], t, g.H);
+        ring_push<C>(L[1], Ln[1], t, g.H);
+        // The later stages run from the first step on; what they compute
+        // before their inputs are valid leaves the rings before any output
+        // uses it.  Only the output is guarded.
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                La[j] = Lb[j];
-                Lb[j] = Lc[j];
-                Lc[j] = Ln[j];
-            }
-            // The later stages run from the first step on; what they compute
-            // before their inputs are valid is shifted out of the rings before
-            // any output uses it.  Only the output row is guarded.
-            {   // zero-crossing strength of row t - 1
-                const long long r = t0 + si - 1;
-                const bool top = r == 0, bot = r == H - 1;
+        for (int j = 0; j < 2; ++j) {   // zero-crossing strength of row t - 1
+            const Acc c = L[j][1];
+            const Acc lf = bperm(g.aL, c), rt = bperm(g.aR, c);
+            ring_push<C>(Z[j], zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, a.zc_thr[j]), t - 1, g.H);
+        }
+        bool ej = false;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const Acc c = Lb[j];
-                    const Acc up = top ? c : La[j];
-                    const Acc dn = bot ? c : Lc[j];
-                    const Acc lf = bperm(aL, c), rt = bperm(aR, c);
-                    Za[j] = Zb[j];
-                    Zb[j] = Zc[j];
-                    Zc[j] = zc_strength<Acc>(c, up, dn, lf, rt, a.zc_thr[j]);
-                }
-            }
-            {   // extraction of row t - 2: 3x3 deviation of Z against T
-                const long long r = t0 + si - 2;
-                const bool top = r == 0, bot = r == H - 1;
-                bool ej = false;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const double zu = top ? Zb[j] : Za[j];
-                    const double zd = bot ? Zb[j] : Zc[j];
-                    const double cs = zu + Zb[j] + zd;
-                    const double cq = __fma_rn(zu, zu, __fma_rn(Zb[j], Zb[j], zd * zd));
-                    const double S = bperm(aL, cs) + cs + bperm(aR, cs);
-                    const double Q = bperm(aL, cq) + cq + bperm(aR, cq);
-                    // 9 sum z^2 - (sum z)^2 = 72 s^2 for the unbiased s of eq. (2)
-                    const double V = __fma_rn(-S, S, 9.0 * Q);
-                    ej = ej || (V > (j == 0 ? thr72_0 : thr72_1));
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) e[k] = e[k + 1];
-                e[4] = clamp_bits(__ballot(ej), lo_lane, hi_lane);
-            }
-            if (si >= 8) {   // output row t - 4
-                const long long r = t0 + si - 4;
-                uint64_t w[5];
-#pragma unroll
-                for (int d = -2; d <= 2; ++d) {
-                    const long long rr = clampll(r + d, 0, H - 1);
-                    const int k = (int)(rr - r) + 2;
-                    w[d + 2] = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : k == 3 ? e[3] : e[4];
-                }
-                const uint64_t f = a.smooth ? (a.median_size == 3 ? hmed3(w) : hmed5(w)) : w[2];
-                if (outc) {
-                    const int fb = (f & mybit) != 0;
-                    a.out[r * a.out_pitch + xc] = (uint8_t)fb;
-                    fcnt += fb;
-                    ecnt += (w[2] & mybit) != 0;
-                }
-            }
+        for (int j = 0; j < 2; ++j) {   // extraction of row t - 2: 3x3 deviation of Z
+            const double cs = Z[j][0] + Z[j][1] + Z[j][2];
+            const double cq = __fma_rn(Z[j][0], Z[j][0], __fma_rn(Z[j][1], Z[j][1], Z[j][2] * Z[j][2]));
+            const double S = bperm(g.aL, cs) + cs + bperm(g.aR, cs);
+            const double Q = bperm(g.aL, cq) + cq + bperm(g.aR, cq);
+            // 9 sum z^2 - (sum z)^2 = 72 s^2 for the unbiased s of eq. (2)
+            const double V = __fma_rn(-S, S, 9.0 * Q);
+            ej = ej || (V > (j == 0 ? thr72_0 : thr72_1));
+        }
+        ring_push<C>(e, clamp_bits(__ballot(ej), lo_lane, hi_lane), t - 2, g.H);
+        // output row t - 4 (from the ninth step on)
+        uint64_t f;
+        if constexpr (MED == 0) f = e[2];
+        else if constexpr (MED == 3) f = hmed3(e);
+        else f = hmed5(e);
+        if (g.outc && si >= 8) {
+            const int fb = (f & mybit) != 0;
+            *orow = (uint8_t)fb;
+            fcnt += fb;
+            ecnt += (e[2] & mybit) != 0;
+        }
+        orow += opitch;
     };
-    int si0 = 0;
-    for (; si0 + P <= nsteps; si0 += P) {
+    auto run = [&](auto clamp) __attribute__((always_inline)) {
+        int si0 = 0;
+        for (; si0 + P <= nsteps; si0 += P) {
 #pragma unroll
-        for (int ph = 0; ph < P; ++ph) step(si0 + ph);
-    }
-    for (; si0 < nsteps; ++si0) step(si0);
+            for (int ph = 0; ph < P; ++ph) step(si0 + ph, clamp);
+        }
+        for (; si0 < nsteps; ++si0) step(si0, clamp);
+    };
+    // rows t-2 .. t of every step stay inside the image: no clamping needed
+    if (t0 - 2 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
+    else run(bool_c<true>{});
 
+    const int wave = threadIdx.x / kWave;
     const int c0 = wave_sum(ecnt), c1 = wave_sum(fcnt);
-    if (lane == 0) {
+    if (g.lane == 0) {
         redc[0][wave] = c0;
         redc[1][wave] = c1;
     }
@@ -511,15 +571,18 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
 // ------------------------------------------------------------- dispatch
 template <class Acc, int RA, int RB, bool DBG>
 hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
-    const size_t shm = lds_bytes(a.waves, a.rows, kHalo1, RB);
-    hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG>), dim3(a.ntiles), dim3(a.waves * kWave), shm,
+    const size_t shm = lds_bytes(a.rows, kHalo1, RB);
+    hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG>), dim3(a.ntiles), dim3(kTileWaves * kWave), shm,
                        s, a);
     return hipGetLastError();
 }
 template <class Acc, int RA, int RB>
 hipError_t p2(const Pass2Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
-    const size_t shm = lds_bytes(a.waves, a.rows, kHalo2, RB);
-    hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB>), dim3(a.ntiles), dim3(a.waves * kWave), shm, s, a);
+    const size_t shm = lds_bytes(a.rows, kHalo2, RB);
+    const dim3 g(a.ntiles), b(kTileWaves * kWave);
+    if (!a.smooth) hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, 0>), g, b, shm, s, a);
+    else if (a.median_size == 3) hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, 3>), g, b, shm, s, a);
+    else hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, 5>), g, b, shm, s, a);
     return hipGetLastError();
 }
 
