@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=8192, help="scene side (8192 = the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run 5 plain device copies of this many MiB (a known-size "
+                         "kernel for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -161,6 +164,14 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    if args.copy_mib > 0:
+        n = args.copy_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_mib} MiB x 5")
     if not args.no_cpu_baseline:
         import oracle
         log(f"oracle on {host_cores()} host threads ...")

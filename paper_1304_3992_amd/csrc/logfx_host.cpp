@@ -313,6 +313,12 @@ int geometry(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, Geometry &g
     return LOGFX_OK;
 }
 
+// For an integer strength c and a threshold thr >= 0: c > thr <=> c > floor(thr).
+int int_threshold(double thr) {
+    const double f = std::floor(thr);
+    return f >= 2147483647.0 ? 2147483647 : (int)f;
+}
+
 ImageDesc image_desc(const logfx_image *img) {
     ImageDesc d;
     d.data = img->data;
@@ -337,6 +343,7 @@ hipError_t launch_p1(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const lo
     for (int slot = 0; slot < 2; ++slot) {
         const int u = pl.order[slot];
         a.zc_thr[slot] = p->zc_thresh / pl.mi[u].unit;
+        a.zc_thr_i[slot] = int_threshold(a.zc_thr[slot]);
         a.unit[slot] = pl.mi[u].unit;
         a.dbgL[slot] = L ? L[u] : nullptr;
         a.dbgZ[slot] = Z ? Z[u] : nullptr;
@@ -358,7 +365,10 @@ hipError_t launch_p2(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const lo
     std::memset(&a, 0, sizeof a);
     a.img = image_desc(img);
     fill_taps<Taps, V>(pl, a.taps);
-    for (int slot = 0; slot < 2; ++slot) a.zc_thr[slot] = p->zc_thresh / pl.mi[pl.order[slot]].unit;
+    for (int slot = 0; slot < 2; ++slot) {
+        a.zc_thr[slot] = p->zc_thresh / pl.mi[pl.order[slot]].unit;
+        a.zc_thr_i[slot] = int_threshold(a.zc_thr[slot]);
+    }
     a.rows = ctx->tiles.rows2;
     a.tiles_x = g.tiles_x2;
     a.ntiles = g.ntiles2;

@@ -57,6 +57,7 @@ struct Pass1Args {
     ImageDesc img;
     Taps taps;
     double zc_thr[2];      // zero-crossing threshold per mask, grid units
+    int zc_thr_i[2];       // the same for integer strengths: floor, capped at INT_MAX
     int rows;              // output rows per wave strip
     int tiles_x;           // tiles across the image (tile width = kTileWaves * (64 - 2 halo))
     int ntiles;            // tiles in the image (= grid size)
@@ -73,6 +74,7 @@ struct Pass2Args {
     ImageDesc img;
     Taps taps;
     double zc_thr[2];
+    int zc_thr_i[2];
     int rows;
     int tiles_x;
     int ntiles;

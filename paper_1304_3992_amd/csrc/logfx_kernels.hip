@@ -54,6 +54,7 @@ __device__ inline double bperm(int addr, double v) {
 template <class Acc> struct AccOps;
 template <> struct AccOps<int> {
     using Taps = OrbitTapsI;
+    template <class A> static __device__ int thr(const A &a, int j) { return a.zc_thr_i[j]; }
     // v_mad_i32_i24 on the raw tap register: both operands fit 24-bit signed
     // (|k| < 2^23 is checked on the host, o < 2^20), so no sign-extended
     // copies of the taps need to be kept alive.
@@ -62,13 +63,12 @@ template <> struct AccOps<int> {
         asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "s"(k), "v"(o), "v"(acc));
         return r;
     }
-    static __device__ double range(int mx, int mn) { return (double)(mx - mn); }
     static __device__ double to_d(int v) { return (double)v; }
 };
 template <> struct AccOps<double> {
     using Taps = OrbitTapsD;
+    template <class A> static __device__ double thr(const A &a, int j) { return a.zc_thr[j]; }
     static __device__ double mac(double k, int o, double acc) { return __fma_rn(k, (double)o, acc); }
-    static __device__ double range(double mx, double mn) { return mx - mn; }
     static __device__ double to_d(double v) { return v; }
 };
 
@@ -106,21 +106,30 @@ __device__ inline void log_pair(const int (&h)[2 * RB + 1][RB + 1],
     out[1] = l1;
 }
 
+// Opposite strict signs of p and q.
+__device__ inline bool opposite(int p, int q) {
+    // signs in {-1, 0, 1}; only -1 ^ 1 and 1 ^ -1 give -2
+    return (min(max(p, -1), 1) ^ min(max(q, -1), 1)) == -2;
+}
+__device__ inline bool opposite(double p, double q) { return p * q < 0.0; }
+
 // Zero-crossing strength (Sec. 3.2) of centre a with neighbours up, dn, lf,
-// rt; returns the strength if a is a crossing stronger than thr, else 0.
-// For a < 0 the pair (a, q) with q > 0 marks a iff |a| <= |q|, i.e. a + q >= 0
-// (ties go to the negative pixel); for a > 0 it marks a iff a + q < 0.  Taking
-// the largest / smallest neighbour decides "some neighbour" at once.
-template <class Acc>
-__device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, double thr) {
+// rt, in grid units; returns the strength if a is a crossing stronger than
+// thr, else 0.  For a < 0 the pair (a, q) with q > 0 marks a iff
+// |a| <= |q|, i.e. a + q >= 0 (ties go to the negative pixel); for a > 0 it
+// marks a iff a + q < 0.  The largest / smallest neighbour decides "some
+// neighbour" at once.  A zero centre is a crossing when its left/right or
+// up/down neighbours have opposite signs; that test only runs when some
+// lane of the wave holds a zero.  Written without short-circuit logic so
+// that it compiles to straight-line code.
+template <class Acc, class Thr>
+__device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
     const Acc qmax = max(max(up, dn), max(lf, rt));
     const Acc qmin = min(min(up, dn), min(lf, rt));
-    const bool nz = a < 0 ? (a + qmax >= 0) : (a + qmin < 0);
-    const bool zr = (lf < 0 && rt > 0) || (lf > 0 && rt < 0) || (up < 0 && dn > 0) ||
-                    (up > 0 && dn < 0);
-    const bool is = (a != 0) ? nz : zr;
-    const double c = AccOps<Acc>::range(max(a, qmax), min(a, qmin));
-    return (is && c > thr) ? c : 0.0;
+    bool is = ((a < 0) & (a + qmax >= 0)) | ((a > 0) & (a + qmin < 0));
+    if (__ballot(a == 0)) is = is | ((a == 0) & (opposite(lf, rt) | opposite(up, dn)));
+    const Acc c = max(a, qmax) - min(a, qmin);   // exact: |L| < 2^30 (int) or 2^52 (FP64)
+    return AccOps<Acc>::to_d((is & (c > thr)) ? c : Acc(0));
 }
 
 // Lane offset (x4, for ds_bpermute) of the clamped column col.
@@ -351,17 +360,18 @@ __global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Ac
         ring_push<C>(L[1], Ln[1], t, g.H);
         // zero crossings of row t - 1 (valid from the third step on)
         const int r = t - 1;
-        const bool use = g.outc && si >= 2;
+        const bool use = g.outc & (si >= 2);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const Acc c = L[j][1];
             const Acc lf = bperm(g.aL, c), rt = bperm(g.aR, c);
-            const double z = zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, a.zc_thr[j]);
-            if (use) {
-                sz[j] += z;
-                sq[j] = __fma_rn(z, z, sq[j]);
-                cnt[j] += z != 0.0;
-                if constexpr (DBG) {
+            const double z = zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j));
+            const double zu = use ? z : 0.0;
+            sz[j] += zu;
+            sq[j] = __fma_rn(zu, zu, sq[j]);
+            cnt[j] += __popcll(__ballot(zu != 0.0));   // wave-uniform
+            if constexpr (DBG) {
+                if (use) {
                     const long long at = (long long)r * g.W + g.xc;
                     if (a.dbgL[j]) a.dbgL[j][at] = AccOps<Acc>::to_d(c) * a.unit[j];
                     if (a.dbgZ[j]) a.dbgZ[j][at] = z * a.unit[j];
@@ -384,12 +394,11 @@ __global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Ac
     // waves in order.
     const int wave = threadIdx.x / kWave;
     double v[4] = {wave_sum(sz[0]), wave_sum(sz[1]), wave_sum(sq[0]), wave_sum(sq[1])};
-    int c0 = wave_sum(cnt[0]), c1 = wave_sum(cnt[1]);
     if (g.lane == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) red[k][wave] = v[k];
-        redc[0][wave] = c0;
-        redc[1][wave] = c1;
+        redc[0][wave] = cnt[0];
+        redc[1][wave] = cnt[1];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -473,6 +482,7 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
     const int lo_lane = g.base < 0 ? -g.base : 0;
     const int hi_lane = min(max(g.W - 1 - g.base, 0), kWave - 1);
     const uint64_t mybit = 1ull << g.lane;
+    const uint64_t outmask = __ballot(g.outc);
 
     int h[P][RB + 1];
 #pragma unroll
@@ -511,7 +521,8 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
         for (int j = 0; j < 2; ++j) {   // zero-crossing strength of row t - 1
             const Acc c = L[j][1];
             const Acc lf = bperm(g.aL, c), rt = bperm(g.aR, c);
-            ring_push<C>(Z[j], zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, a.zc_thr[j]), t - 1, g.H);
+            ring_push<C>(Z[j], zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j)),
+                         t - 1, g.H);
         }
         bool ej = false;
 #pragma unroll
@@ -530,11 +541,10 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
         if constexpr (MED == 0) f = e[2];
         else if constexpr (MED == 3) f = hmed3(e);
         else f = hmed5(e);
-        if (g.outc && si >= 8) {
-            const int fb = (f & mybit) != 0;
-            *orow = (uint8_t)fb;
-            fcnt += fb;
-            ecnt += (e[2] & mybit) != 0;
+        if (si >= 8) {
+            if (g.outc) *orow = (uint8_t)((f & mybit) != 0);
+            fcnt += __popcll(f & outmask);       // wave-uniform counts
+            ecnt += __popcll(e[2] & outmask);
         }
         orow += opitch;
     };
@@ -551,10 +561,9 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
     else run(bool_c<true>{});
 
     const int wave = threadIdx.x / kWave;
-    const int c0 = wave_sum(ecnt), c1 = wave_sum(fcnt);
     if (g.lane == 0) {
-        redc[0][wave] = c0;
-        redc[1][wave] = c1;
+        redc[0][wave] = ecnt;
+        redc[1][wave] = fcnt;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
