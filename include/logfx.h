@@ -162,13 +162,39 @@ int logfx_extract(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p,
 int logfx_extract_maps(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p,
                        double *L1, double *L2, double *Z1, double *Z2, void *stream);
 
+/* Many images in one call (a batch of scene tiles of uneven sizes, or the
+ * bands of a multispectral scene, Sec. 4.2).  Every image runs the whole
+ * pipeline on its own (its own global deviation and thresholds); all share
+ * the parameters, dtype and bits.  imgs: HOST array of n descriptors;
+ * outs: HOST array of n DEVICE output pointers (height*width bytes each).
+ * reps: HOST array of n reports or NULL (given: the call waits).
+ * The tiles of all images run in one launch per pass: one workgroup per
+ * tile, or, with LOGFX_OPT_PERSISTENT set, a persistent grid of the
+ * workgroups that fit on the device walking all tiles; the launches are
+ * replayed from a captured hipGraph unless LOGFX_OPT_GRAPH is 0 (the graph
+ * is re-captured when the batch geometry or parameters change).  The image table is uploaded from pinned memory on
+ * `stream` before the launches. */
+int logfx_extract_batch(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
+                        uint8_t *const *outs, logfx_report *reps, void *stream);
+
+/* Context options (logfx_set_option / logfx_get_option). */
+enum {
+    LOGFX_OPT_ROWS1 = 1,      /* output rows per wave strip in pass 1 (1..1024, default 64) */
+    LOGFX_OPT_ROWS2 = 2,      /* the same for pass 2 (default 64) */
+    LOGFX_OPT_PERSISTENT = 3, /* batches: 1 = persistent launch, 0 = one workgroup per tile (default) */
+    LOGFX_OPT_GRAPH = 4       /* batches: 1 = replay a captured hipGraph (default), 0 = direct launches */
+};
+int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value);
+int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value);
+
 /* Kernel timing (the split of Table 6 in Sec. 7 between transfers and
- * kernel time, refined per kernel).  While enabled, every logfx_extract on
+ * kernel time, refined per kernel).  While enabled, every extract call on
  * the context records HIP events around its kernels on the call's stream.
- * logfx_timing_read waits for the recorded events, returns the summed
- * milliseconds of pass 1, the finalize kernel and pass 2 in ms_out[0..2]
- * and the number of timed calls in *calls_out (nullable), and starts a new
- * accumulation.  Enabling or disabling also starts a new accumulation. */
+ * logfx_timing_read waits for the recorded events and returns summed
+ * milliseconds in ms_out[0..3]: pass 1, the finalize kernel, pass 2 (direct
+ * launches only; a graph replay is timed as a whole) and the whole call;
+ * *calls_out (nullable) receives the number of timed calls.  It starts a new
+ * accumulation, as does enabling or disabling. */
 int logfx_timing_enable(logfx_ctx *ctx, int on);
 int logfx_timing_read(logfx_ctx *ctx, double *ms_out, int64_t *calls_out);
 

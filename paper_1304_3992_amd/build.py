@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblogfx.so")
-SOURCES = ["logfx_host.cpp", "logfx_kernels.hip"]
+# Mask radius pairs (ra <= rb) instantiated by logfx_kernels_inst.hip.
+RADII = [(1, 1), (1, 2), (2, 2), (1, 3), (2, 3), (3, 3), (1, 4), (2, 4), (3, 4), (4, 4)]
 ARCH = os.environ.get("LOGFX_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.
@@ -23,24 +24,39 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
+def _units():
+    """(source, object, extra flags) of every translation unit."""
+    b = os.path.join(HERE, "_build")
+    units = [("logfx_host.cpp", os.path.join(b, "logfx_host.o"), []),
+             ("logfx_dispatch.hip", os.path.join(b, "logfx_dispatch.o"), ["-x", "hip"])]
+    for ra, rb in RADII:
+        units.append(("logfx_kernels_inst.hip", os.path.join(b, f"logfx_kernels_r{ra}{rb}.o"),
+                      ["-x", "hip", f"-DLOGFX_RA={ra}", f"-DLOGFX_RB={rb}"]))
+    return units
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
-    bdir = os.path.join(HERE, "_build")
-    os.makedirs(bdir, exist_ok=True)
-    procs = []
-    for src in SOURCES:
-        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-               *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((subprocess.Popen(cmd), cmd))
-        objs.append(obj)
-    for p, cmd in procs:
-        if p.wait() != 0:
-            raise RuntimeError("compile failed: " + " ".join(cmd))
+    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    pending = list(_units())
+    running, objs = [], []
+    while pending or running:
+        while pending and len(running) < jobs:
+            src, obj, extra = pending.pop(0)
+            cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *extra,
+                   "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), cmd))
+            objs.append(obj)
+        p, cmd = running.pop(0)
+        err = p.communicate()[1]
+        err = "\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l)
+        if p.returncode != 0:
+            raise RuntimeError("compile failed: " + " ".join(cmd) + "\n" + err)
+        if err.strip() and verbose:
+            print(err, flush=True)
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:

@@ -48,21 +48,37 @@ struct logfx_ctx {
     int device = 0;
     std::string err;
     TileCfg tiles;
+    bool persistent = false;         // batches: one resident grid walks all tiles
+    bool graph = true;               // batches: replay a captured hipGraph
     // device scratch
     double *partials = nullptr;      // [cap1][4]
     long long *counts1 = nullptr;    // [cap1][2]
     int *counts2 = nullptr;          // [cap2][2]
-    DevStats *stats = nullptr;
-    long long cap1 = 0, cap2 = 0;
-    // pinned host mirror for reports
+    DevStats *stats = nullptr;       // [capn]
+    ImageJob *jobs = nullptr;        // [capn] batch image table
+    int *owner1 = nullptr;           // [cap1] image of each pass-1 tile
+    int *owner2 = nullptr;           // [cap2] image of each pass-2 tile
+    long long cap1 = 0, cap2 = 0, capn = 0;
+    // pinned host memory: report mirrors and the staging of the batch tables
     DevStats *h_stats = nullptr;
     int *h_counts2 = nullptr;
-    long long h_cap2 = 0;
+    long long h_capn = 0, h_cap2 = 0;
+    ImageJob *h_jobs = nullptr;
+    int *h_owner1 = nullptr, *h_owner2 = nullptr;
+    long long h_tcapn = 0, h_tcap1 = 0, h_tcap2 = 0;
+    hipEvent_t staged = nullptr;     // last upload of the staging buffers
+    // captured batch graph and the launch arguments it was captured with
+    hipStream_t capture = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;
     // kernel timing: 4 events per timed call (start, after pass 1, after
-    // finalize, after pass 2), reused across accumulations
+    // finalize, after pass 2; a graph replay records start and end only),
+    // reused across accumulations
     bool timing = false;
     std::vector<hipEvent_t> events;
     long long timed_calls = 0;
+    std::vector<char> timed_graph;   // per timed call: 1 if it was a graph replay
     int alloc_count = 0;
     int fail_alloc_at = -1;          // test hook: LOGFX_FAIL_ALLOC=n fails the n-th allocation
 };
@@ -112,40 +128,59 @@ int dev_alloc(logfx_ctx *ctx, T **p, size_t count) {
     return LOGFX_OK;
 }
 
-int ensure_scratch(logfx_ctx *ctx, long long n1, long long n2) {
+// Replace a device buffer by one of `count` elements.
+template <class T>
+int realloc_dev(logfx_ctx *ctx, T *&p, long long count) {
+    (void)hipFree(p);
+    p = nullptr;
+    return dev_alloc(ctx, &p, (size_t)count);
+}
+
+// Grow-only per-context scratch for n1 pass-1 tiles, n2 pass-2 tiles and
+// nimg images.
+int ensure_scratch(logfx_ctx *ctx, long long n1, long long n2, long long nimg) {
     int rc;
-    if (!ctx->stats && (rc = dev_alloc(ctx, &ctx->stats, 1)) != LOGFX_OK) return rc;
     if (n1 > ctx->cap1) {
-        (void)hipFree(ctx->partials);
-        (void)hipFree(ctx->counts1);
-        ctx->partials = nullptr, ctx->counts1 = nullptr, ctx->cap1 = 0;
-        if ((rc = dev_alloc(ctx, &ctx->partials, (size_t)n1 * 4)) != LOGFX_OK) return rc;
-        if ((rc = dev_alloc(ctx, &ctx->counts1, (size_t)n1 * 2)) != LOGFX_OK) return rc;
+        ctx->cap1 = 0;
+        if ((rc = realloc_dev(ctx, ctx->partials, n1 * 4)) != LOGFX_OK ||
+            (rc = realloc_dev(ctx, ctx->counts1, n1 * 2)) != LOGFX_OK ||
+            (rc = realloc_dev(ctx, ctx->owner1, n1)) != LOGFX_OK)
+            return rc;
         ctx->cap1 = n1;
     }
     if (n2 > ctx->cap2) {
-        (void)hipFree(ctx->counts2);
-        ctx->counts2 = nullptr, ctx->cap2 = 0;
-        if ((rc = dev_alloc(ctx, &ctx->counts2, (size_t)n2 * 2)) != LOGFX_OK) return rc;
+        ctx->cap2 = 0;
+        if ((rc = realloc_dev(ctx, ctx->counts2, n2 * 2)) != LOGFX_OK ||
+            (rc = realloc_dev(ctx, ctx->owner2, n2)) != LOGFX_OK)
+            return rc;
         ctx->cap2 = n2;
+    }
+    if (nimg > ctx->capn) {
+        ctx->capn = 0;
+        if ((rc = realloc_dev(ctx, ctx->stats, nimg)) != LOGFX_OK ||
+            (rc = realloc_dev(ctx, ctx->jobs, nimg)) != LOGFX_OK)
+            return rc;
+        ctx->capn = nimg;
     }
     return LOGFX_OK;
 }
 
-int ensure_host(logfx_ctx *ctx, long long n2) {
-    if (!ctx->h_stats) {
-        hipError_t e = hipHostMalloc((void **)&ctx->h_stats, sizeof(DevStats), hipHostMallocDefault);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipHostMalloc");
-    }
-    if (n2 > ctx->h_cap2) {
-        if (ctx->h_counts2) (void)hipHostFree(ctx->h_counts2);
-        ctx->h_counts2 = nullptr, ctx->h_cap2 = 0;
-        hipError_t e = hipHostMalloc((void **)&ctx->h_counts2, (size_t)n2 * 2 * sizeof(int),
-                                     hipHostMallocDefault);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipHostMalloc");
-        ctx->h_cap2 = n2;
-    }
+template <class T>
+int grow_host(logfx_ctx *ctx, T *&p, long long &cap, long long n) {
+    if (n <= cap) return LOGFX_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc((void **)&p, (size_t)n * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipHostMalloc");
+    cap = n;
     return LOGFX_OK;
+}
+
+int ensure_host(logfx_ctx *ctx, long long nimg, long long n2) {
+    int rc;
+    if ((rc = grow_host(ctx, ctx->h_stats, ctx->h_capn, nimg)) != LOGFX_OK) return rc;
+    return grow_host(ctx, ctx->h_counts2, ctx->h_cap2, n2 * 2);
 }
 
 // Events of timed call number `call` (created on first use).
@@ -291,25 +326,26 @@ void fill_taps(const Plan &pl, Taps &t) {
     }
 }
 
-struct Geometry {
+// ------------------------------------------------------------ one call
+// Tiling of one image in both passes.
+struct ImageTiles {
     int tiles_x1, ntiles1, tiles_x2, ntiles2;
 };
 
-int geometry(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, Geometry &g) {
-    const TileCfg &t = ctx->tiles;
+int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, ImageTiles &t) {
+    const TileCfg &c = ctx->tiles;
     const long long H = img->height, W = img->width;
     if (H >= (1LL << 30) || W >= (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image sides must be below 2^30");
-    const long long tw1 = (long long)kTileWaves * (kWave - 2 * kHalo1);
-    const long long tw2 = (long long)kTileWaves * (kWave - 2 * kHalo2);
-    const long long tx1 = (W + tw1 - 1) / tw1, ty1 = (H + t.rows1 - 1) / t.rows1;
-    const long long tx2 = (W + tw2 - 1) / tw2, ty2 = (H + t.rows2 - 1) / t.rows2;
-    if (tx1 * ty1 > 0x7fffffffLL || tx2 * ty2 > 0x7fffffffLL)
+    const long long tw1 = tile_out_width(kHalo1), tw2 = tile_out_width(kHalo2);
+    const long long tx1 = (W + tw1 - 1) / tw1, ty1 = (H + c.rows1 - 1) / c.rows1;
+    const long long tx2 = (W + tw2 - 1) / tw2, ty2 = (H + c.rows2 - 1) / c.rows2;
+    if (tx1 * ty1 > (1LL << 30) || tx2 * ty2 > (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image too large for one launch");
-    if (lds_bytes(t.rows1, kHalo1, pl.rb) > 65536 || lds_bytes(t.rows2, kHalo2, pl.rb) > 65536)
+    if (lds_bytes(c.rows1, kHalo1, pl.rb) > 65536 || lds_bytes(c.rows2, kHalo2, pl.rb) > 65536)
         return set_err(ctx, LOGFX_EUNSUPPORTED, "tile configuration exceeds 64 KiB of LDS");
-    g.tiles_x1 = (int)tx1, g.ntiles1 = (int)(tx1 * ty1);
-    g.tiles_x2 = (int)tx2, g.ntiles2 = (int)(tx2 * ty2);
+    t.tiles_x1 = (int)tx1, t.ntiles1 = (int)(tx1 * ty1);
+    t.tiles_x2 = (int)tx2, t.ntiles2 = (int)(tx2 * ty2);
     return LOGFX_OK;
 }
 
@@ -332,54 +368,294 @@ ImageDesc image_desc(const logfx_image *img) {
     return d;
 }
 
-template <class Taps, class V>
-hipError_t launch_p1(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const logfx_image *img,
-                     const logfx_params *p, double *const L[2], double *const Z[2], hipStream_t s) {
-    Pass1Args<Taps> a;
-    std::memset(&a, 0, sizeof a);
-    a.img = image_desc(img);
-    fill_taps<Taps, V>(pl, a.taps);
-    bool dbg = false;
-    for (int slot = 0; slot < 2; ++slot) {
-        const int u = pl.order[slot];
-        a.zc_thr[slot] = p->zc_thresh / pl.mi[u].unit;
-        a.zc_thr_i[slot] = int_threshold(a.zc_thr[slot]);
-        a.unit[slot] = pl.mi[u].unit;
-        a.dbgL[slot] = L ? L[u] : nullptr;
-        a.dbgZ[slot] = Z ? Z[u] : nullptr;
-        dbg = dbg || a.dbgL[slot] || a.dbgZ[slot];
+// Everything one call enqueues.
+struct Call {
+    Plan pl;
+    Launch L;
+    int n = 1;
+    std::vector<ImageTiles> tiles;
+};
+
+// Validates the images against the parameters, tiles them and (for a batch)
+// uploads the image table and tile owners.
+int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p,
+            uint8_t *const *outs, bool need_out, Call &c, hipStream_t s) {
+    if (n < 1 || !imgs) return set_err(ctx, LOGFX_EINVAL, "no images");
+    int rc = check_all(ctx, &imgs[0], p, c.pl);
+    if (rc != LOGFX_OK) return rc;
+    const int bits0 = imgs[0].bits == 0 ? (imgs[0].dtype == LOGFX_U8 ? 8 : 16) : imgs[0].bits;
+    c.n = n;
+    c.tiles.resize(n);
+    long long t1 = 0, t2 = 0;
+    for (int i = 0; i < n; ++i) {
+        if (i > 0) {
+            Plan tmp;
+            if ((rc = check_all(ctx, &imgs[i], p, tmp)) != LOGFX_OK) return rc;
+            const int bi = imgs[i].bits == 0 ? (imgs[i].dtype == LOGFX_U8 ? 8 : 16) : imgs[i].bits;
+            if (imgs[i].dtype != imgs[0].dtype || bi != bits0)
+                return set_err(ctx, LOGFX_EINVAL, "image %d: all images of a batch must share "
+                                                  "dtype and bits", i);
+        }
+        if (need_out && (!outs || !outs[i])) return set_err(ctx, LOGFX_EINVAL, "output %d is NULL", i);
+        if ((rc = tile_image(ctx, &imgs[i], c.pl, c.tiles[i])) != LOGFX_OK) return rc;
+        t1 += c.tiles[i].ntiles1;
+        t2 += c.tiles[i].ntiles2;
     }
-    a.rows = ctx->tiles.rows1;
-    a.tiles_x = g.tiles_x1;
-    a.ntiles = g.ntiles1;
-    a.partials = ctx->partials;
-    a.counts = ctx->counts1;
-    if constexpr (sizeof(V) == sizeof(int)) return launch_pass1_i(pl.ra, pl.rb, a, dbg, s);
-    else return launch_pass1_d(pl.ra, pl.rb, a, dbg, s);
+    if (t1 >= (1LL << 31) || t2 >= (1LL << 31))
+        return set_err(ctx, LOGFX_EUNSUPPORTED, "too many tiles for one launch");
+    if ((rc = ensure_scratch(ctx, t1, t2, n)) != LOGFX_OK) return rc;
+    std::memset(&c.L, 0, sizeof c.L);
+    c.L.nimg = n;
+    c.L.total1 = (int)t1;
+    c.L.total2 = (int)t2;
+    auto job = [&](int i, int b1, int b2) {
+        ImageJob j;
+        std::memset(&j, 0, sizeof j);
+        j.img = image_desc(&imgs[i]);
+        j.out = outs ? outs[i] : nullptr;
+        j.out_pitch = imgs[i].width;
+        j.tiles_x1 = c.tiles[i].tiles_x1;
+        j.tiles_x2 = c.tiles[i].tiles_x2;
+        j.ntiles1 = c.tiles[i].ntiles1;
+        j.ntiles2 = c.tiles[i].ntiles2;
+        j.base1 = b1;
+        j.base2 = b2;
+        return j;
+    };
+    if (n == 1) {
+        c.L.one = job(0, 0, 0);
+        return LOGFX_OK;
+    }
+    // batch: stage the tables in pinned memory (after the previous upload
+    // from it has finished) and upload them on the call's stream
+    if (ctx->staged && (rc = hipEventSynchronize(ctx->staged)) != hipSuccess)
+        return hip_err(ctx, (hipError_t)rc, "hipEventSynchronize");
+    if ((rc = grow_host(ctx, ctx->h_jobs, ctx->h_tcapn, n)) != LOGFX_OK ||
+        (rc = grow_host(ctx, ctx->h_owner1, ctx->h_tcap1, t1)) != LOGFX_OK ||
+        (rc = grow_host(ctx, ctx->h_owner2, ctx->h_tcap2, t2)) != LOGFX_OK)
+        return rc;
+    int b1 = 0, b2 = 0;
+    for (int i = 0; i < n; ++i) {
+        ctx->h_jobs[i] = job(i, b1, b2);
+        for (int k = 0; k < c.tiles[i].ntiles1; ++k) ctx->h_owner1[b1 + k] = i;
+        for (int k = 0; k < c.tiles[i].ntiles2; ++k) ctx->h_owner2[b2 + k] = i;
+        b1 += c.tiles[i].ntiles1;
+        b2 += c.tiles[i].ntiles2;
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ctx->jobs, ctx->h_jobs, sizeof(ImageJob) * n, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->owner1, ctx->h_owner1, sizeof(int) * t1, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->owner2, ctx->h_owner2, sizeof(int) * t2, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+        return hip_err(ctx, e, "table upload");
+    if (!ctx->staged && (e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming)) != hipSuccess)
+        return hip_err(ctx, e, "hipEventCreate");
+    if ((e = hipEventRecord(ctx->staged, s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
+    c.L.jobs = ctx->jobs;
+    c.L.owner1 = ctx->owner1;
+    c.L.owner2 = ctx->owner2;
+    return LOGFX_OK;
 }
 
+// The three launches of one call, built once so that a graph replay can
+// compare them with the captured ones.
+struct Launches {
+    union {
+        Pass1Args<OrbitTapsI> i;
+        Pass1Args<OrbitTapsD> d;
+    } p1;
+    union {
+        Pass2Args<OrbitTapsI> i;
+        Pass2Args<OrbitTapsD> d;
+    } p2;
+    FinalizeArgs fin;
+    int grid1, grid2;
+    int path, ra, rb;
+    bool dbg;
+};
+
 template <class Taps, class V>
-hipError_t launch_p2(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const logfx_image *img,
-                     const logfx_params *p, uint8_t *out, hipStream_t s) {
-    Pass2Args<Taps> a;
-    std::memset(&a, 0, sizeof a);
-    a.img = image_desc(img);
-    fill_taps<Taps, V>(pl, a.taps);
+void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *const L[2],
+               double *const Z[2], Pass1Args<Taps> &a1, Pass2Args<Taps> &a2, bool &dbg) {
+    std::memset(&a1, 0, sizeof a1);
+    std::memset(&a2, 0, sizeof a2);
+    a1.L = a2.L = c.L;
+    fill_taps<Taps, V>(c.pl, a1.taps);
+    fill_taps<Taps, V>(c.pl, a2.taps);
+    dbg = false;
     for (int slot = 0; slot < 2; ++slot) {
-        a.zc_thr[slot] = p->zc_thresh / pl.mi[pl.order[slot]].unit;
-        a.zc_thr_i[slot] = int_threshold(a.zc_thr[slot]);
+        const int u = c.pl.order[slot];
+        a1.zc_thr[slot] = a2.zc_thr[slot] = p->zc_thresh / c.pl.mi[u].unit;
+        a1.zc_thr_i[slot] = a2.zc_thr_i[slot] = int_threshold(a1.zc_thr[slot]);
+        a1.unit[slot] = c.pl.mi[u].unit;
+        a1.dbgL[slot] = L ? L[u] : nullptr;
+        a1.dbgZ[slot] = Z ? Z[u] : nullptr;
+        dbg = dbg || a1.dbgL[slot] || a1.dbgZ[slot];
     }
-    a.rows = ctx->tiles.rows2;
-    a.tiles_x = g.tiles_x2;
-    a.ntiles = g.ntiles2;
-    a.stats = ctx->stats;
-    a.out = out;
-    a.out_pitch = img->width;
-    a.smooth = p->smooth == LOGFX_SMOOTH_ALWAYS;
-    a.median_size = p->median_size;
-    a.counts = ctx->counts2;
-    if constexpr (sizeof(V) == sizeof(int)) return launch_pass2_i(pl.ra, pl.rb, a, s);
-    else return launch_pass2_d(pl.ra, pl.rb, a, s);
+    a1.rows = ctx->tiles.rows1;
+    a1.partials = ctx->partials;
+    a1.counts = ctx->counts1;
+    a2.rows = ctx->tiles.rows2;
+    a2.stats = ctx->stats;
+    a2.counts = ctx->counts2;
+    a2.smooth = p->smooth == LOGFX_SMOOTH_ALWAYS;
+    a2.median_size = p->median_size;
+}
+
+hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, bool maps_only) {
+    hipError_t e;
+    const bool i32 = k.path == LOGFX_PATH_INT32;
+    e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, k.dbg, k.grid1, s)
+            : launch_pass1_d(k.ra, k.rb, k.p1.d, k.dbg, k.grid1, s);
+    if (e != hipSuccess || maps_only) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    if ((e = launch_finalize(k.fin, s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    return i32 ? launch_pass2_i(k.ra, k.rb, k.p2.i, k.grid2, s)
+               : launch_pass2_d(k.ra, k.rb, k.p2.d, k.grid2, s);
+}
+
+int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double *const L[2],
+                   double *const Z[2], Launches &k) {
+    std::memset(&k, 0, sizeof k);
+    k.path = c.pl.path;
+    k.ra = c.pl.ra;
+    k.rb = c.pl.rb;
+    if (k.path == LOGFX_PATH_INT32) fill_args<OrbitTapsI, int>(c, ctx, p, L, Z, k.p1.i, k.p2.i, k.dbg);
+    else fill_args<OrbitTapsD, double>(c, ctx, p, L, Z, k.p1.d, k.p2.d, k.dbg);
+    k.fin.L = c.L;
+    k.fin.partials = ctx->partials;
+    k.fin.counts = ctx->counts1;
+    k.fin.std_mode = p->std_mode;
+    k.fin.std_k = p->std_k;
+    for (int slot = 0; slot < 2; ++slot) k.fin.abs_thr[slot] = p->std_k / c.pl.mi[c.pl.order[slot]].unit;
+    k.fin.stats = ctx->stats;
+    k.grid1 = c.L.total1;
+    k.grid2 = c.L.total2;
+    if (c.n > 1 && ctx->persistent && !k.dbg) {
+        // a persistent launch: as many workgroups as fit on the device
+        int m1 = 0, m2 = 0;
+        const bool i32 = k.path == LOGFX_PATH_INT32;
+        hipError_t e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, false, 0, nullptr, &m1)
+                           : launch_pass1_d(k.ra, k.rb, k.p1.d, false, 0, nullptr, &m1);
+        if (e == hipSuccess)
+            e = i32 ? launch_pass2_i(k.ra, k.rb, k.p2.i, 0, nullptr, &m2)
+                    : launch_pass2_d(k.ra, k.rb, k.p2.d, 0, nullptr, &m2);
+        if (e != hipSuccess) return hip_err(ctx, e, "occupancy query");
+        if (m1 > 0) k.grid1 = std::min(k.grid1, m1);
+        if (m2 > 0) k.grid2 = std::min(k.grid2, m2);
+    }
+    return LOGFX_OK;
+}
+
+// Replays the context's graph when the launches equal the captured ones,
+// else captures a new graph first.
+int graph_launch(logfx_ctx *ctx, const Launches &k, hipStream_t s) {
+    const unsigned char *kb = reinterpret_cast<const unsigned char *>(&k);
+    hipError_t e;
+    if (!ctx->gexec || ctx->gkey.size() != sizeof k || std::memcmp(ctx->gkey.data(), kb, sizeof k) != 0) {
+        if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+        if (ctx->g) (void)hipGraphDestroy(ctx->g);
+        ctx->gexec = nullptr;
+        ctx->g = nullptr;
+        ctx->gkey.clear();
+        if (!ctx->capture && (e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking)) != hipSuccess)
+            return hip_err(ctx, e, "hipStreamCreate");
+        if ((e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_err(ctx, e, "hipStreamBeginCapture");
+        hipError_t le = launch_all(k, ctx->capture, nullptr, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->capture, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_err(ctx, le, "captured launch");
+        }
+        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_err(ctx, e, "hipGraphInstantiate");
+        }
+        ctx->g = g;
+        ctx->gexec = x;
+        ctx->gkey.assign(kb, kb + sizeof k);
+    }
+    if ((e = hipGraphLaunch(ctx->gexec, s)) != hipSuccess) return hip_err(ctx, e, "hipGraphLaunch");
+    return LOGFX_OK;
+}
+
+int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, logfx_report *reps,
+                 hipStream_t s) {
+    int rc;
+    if ((rc = ensure_host(ctx, c.n, c.L.total2)) != LOGFX_OK) return rc;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ctx->h_stats, ctx->stats, sizeof(DevStats) * c.n, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->h_counts2, ctx->counts2, sizeof(int) * 2 * (size_t)c.L.total2,
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_err(ctx, e, "report copy");
+    long long b2 = 0;
+    for (int i = 0; i < c.n; ++i) {
+        logfx_report &r = reps[i];
+        std::memset(&r, 0, sizeof r);
+        const ImageJob &j = c.n == 1 ? c.L.one : ctx->h_jobs[i];
+        r.pixels = j.img.H * j.img.W;
+        for (int slot = 0; slot < 2; ++slot) {
+            const int u = c.pl.order[slot];
+            const double unit = c.pl.mi[u].unit;
+            r.sigma_g[u] = ctx->h_stats[i].sigma[slot] * unit;
+            r.thresh[u] = ctx->h_stats[i].thresh[slot] * unit;
+            r.zc_count[u] = ctx->h_stats[i].zc[slot];
+        }
+        for (int t = 0; t < c.tiles[i].ntiles2; ++t) {
+            r.extracted += ctx->h_counts2[2 * (b2 + t)];
+            r.output += ctx->h_counts2[2 * (b2 + t) + 1];
+        }
+        b2 += c.tiles[i].ntiles2;
+        r.path = c.pl.path;
+        r.smoothed = p->smooth == LOGFX_SMOOTH_ALWAYS;
+    }
+    return LOGFX_OK;
+}
+
+int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, uint8_t *const *outs,
+        double *const maps_L[2], double *const maps_Z[2], logfx_report *reps, void *stream) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    const bool maps = maps_L != nullptr;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    Call c;
+    int rc = prepare(ctx, n, imgs, p, outs, !maps, c, s);
+    if (rc != LOGFX_OK) return rc;
+    Launches k;
+    if ((rc = build_launches(ctx, c, p, maps_L, maps_Z, k)) != LOGFX_OK) return rc;
+    hipError_t e;
+    const bool use_graph = n > 1 && ctx->graph && !maps;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool timed = ctx->timing && !maps;
+    if (timed) {
+        if ((rc = timing_events(ctx, ctx->timed_calls, ev)) != LOGFX_OK) return rc;
+        if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
+    }
+    if (use_graph) {
+        if ((rc = graph_launch(ctx, k, s)) != LOGFX_OK) return rc;
+    } else if ((e = launch_all(k, s, timed ? ev : nullptr, maps)) != hipSuccess) {
+        return hip_err(ctx, e, "kernel launch");
+    }
+    if (maps) return LOGFX_OK;
+    if (timed) {
+        if ((e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
+        ctx->timed_graph.resize(ctx->timed_calls + 1);
+        ctx->timed_graph[ctx->timed_calls] = use_graph;
+        ++ctx->timed_calls;
+    }
+    if (reps) return fill_reports(ctx, c, p, reps, s);
+    return LOGFX_OK;
 }
 
 }  // namespace
@@ -387,7 +663,7 @@ hipError_t launch_p2(const Plan &pl, const Geometry &g, logfx_ctx *ctx, const lo
 // ===================================================================== ABI
 extern "C" {
 
-const char *logfx_version(void) { return "liblogfx 0.1 (gfx950)"; }
+const char *logfx_version(void) { return "liblogfx 0.2 (gfx950)"; }
 
 const char *logfx_last_error(const logfx_ctx *ctx) {
     return ctx ? ctx->err.c_str() : g_thread_error.c_str();
@@ -416,12 +692,25 @@ int logfx_destroy(logfx_ctx *ctx) {
     if (!ctx) return LOGFX_OK;
     {
         DeviceGuard g(ctx->device);
+        if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+        if (ctx->g) (void)hipGraphDestroy(ctx->g);
+        if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+        if (ctx->staged) {
+            (void)hipEventSynchronize(ctx->staged);
+            (void)hipEventDestroy(ctx->staged);
+        }
         (void)hipFree(ctx->partials);
         (void)hipFree(ctx->counts1);
         (void)hipFree(ctx->counts2);
         (void)hipFree(ctx->stats);
+        (void)hipFree(ctx->jobs);
+        (void)hipFree(ctx->owner1);
+        (void)hipFree(ctx->owner2);
         if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
         if (ctx->h_counts2) (void)hipHostFree(ctx->h_counts2);
+        if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
+        if (ctx->h_owner1) (void)hipHostFree(ctx->h_owner1);
+        if (ctx->h_owner2) (void)hipHostFree(ctx->h_owner2);
         for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
     }
     delete ctx;
@@ -476,92 +765,48 @@ int logfx_check_params(const logfx_image *img, const logfx_params *p, int32_t *p
     return rc;
 }
 
-static int run(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, uint8_t *out,
-               double *const maps_L[2], double *const maps_Z[2], logfx_report *rep, void *stream) {
-    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
-    ctx->err.clear();
-    Plan pl;
-    int rc = check_all(ctx, img, p, pl);
-    if (rc != LOGFX_OK) return rc;
-    const bool maps = maps_L != nullptr;
-    if (!maps && !out) return set_err(ctx, LOGFX_EINVAL, "out is NULL");
-    Geometry g;
-    if ((rc = geometry(ctx, img, pl, g)) != LOGFX_OK) return rc;
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
-    if ((rc = ensure_scratch(ctx, g.ntiles1, g.ntiles2)) != LOGFX_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    const bool timed = ctx->timing && !maps;
-    if (timed) {
-        if ((rc = timing_events(ctx, ctx->timed_calls, ev)) != LOGFX_OK) return rc;
-        if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
-    }
-    const bool i32 = pl.path == LOGFX_PATH_INT32;
-    e = i32 ? launch_p1<OrbitTapsI, int>(pl, g, ctx, img, p, maps_L, maps_Z, s)
-            : launch_p1<OrbitTapsD, double>(pl, g, ctx, img, p, maps_L, maps_Z, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "pass-1 launch");
-    if (maps) return LOGFX_OK;
-    if (timed && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
-
-    FinalizeArgs f;
-    std::memset(&f, 0, sizeof f);
-    f.partials = ctx->partials;
-    f.counts = ctx->counts1;
-    f.ntiles = g.ntiles1;
-    f.n = img->height * img->width;
-    f.std_mode = p->std_mode;
-    f.std_k = p->std_k;
-    for (int slot = 0; slot < 2; ++slot) f.abs_thr[slot] = p->std_k / pl.mi[pl.order[slot]].unit;
-    f.stats = ctx->stats;
-    if ((e = launch_finalize(f, s)) != hipSuccess) return hip_err(ctx, e, "finalize launch");
-    if (timed && (e = hipEventRecord(ev[2], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
-
-    e = i32 ? launch_p2<OrbitTapsI, int>(pl, g, ctx, img, p, out, s)
-            : launch_p2<OrbitTapsD, double>(pl, g, ctx, img, p, out, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "pass-2 launch");
-    if (timed) {
-        if ((e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
-        ++ctx->timed_calls;
-    }
-
-    if (rep) {
-        if ((rc = ensure_host(ctx, g.ntiles2)) != LOGFX_OK) return rc;
-        if ((e = hipMemcpyAsync(ctx->h_stats, ctx->stats, sizeof(DevStats), hipMemcpyDeviceToHost,
-                                s)) != hipSuccess ||
-            (e = hipMemcpyAsync(ctx->h_counts2, ctx->counts2, (size_t)g.ntiles2 * 2 * sizeof(int),
-                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_err(ctx, e, "report copy");
-        std::memset(rep, 0, sizeof *rep);
-        rep->pixels = f.n;
-        for (int slot = 0; slot < 2; ++slot) {
-            const int u = pl.order[slot];
-            const double unit = pl.mi[u].unit;
-            rep->sigma_g[u] = ctx->h_stats->sigma[slot] * unit;
-            rep->thresh[u] = ctx->h_stats->thresh[slot] * unit;
-            rep->zc_count[u] = ctx->h_stats->zc[slot];
-        }
-        for (int t = 0; t < g.ntiles2; ++t) {
-            rep->extracted += ctx->h_counts2[2 * t];
-            rep->output += ctx->h_counts2[2 * t + 1];
-        }
-        rep->path = pl.path;
-        rep->smoothed = p->smooth == LOGFX_SMOOTH_ALWAYS;
-    }
-    return LOGFX_OK;
-}
-
 int logfx_extract(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, uint8_t *out,
                   logfx_report *rep, void *stream) {
-    return run(ctx, img, p, out, nullptr, nullptr, rep, stream);
+    if (!img) return set_err(ctx, LOGFX_EINVAL, "image is NULL");
+    uint8_t *outs[1] = {out};
+    return run(ctx, 1, img, p, outs, nullptr, nullptr, rep, stream);
+}
+
+int logfx_extract_batch(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
+                        uint8_t *const *outs, logfx_report *reps, void *stream) {
+    return run(ctx, n, imgs, p, outs, nullptr, nullptr, reps, stream);
 }
 
 int logfx_extract_maps(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, double *L1,
                        double *L2, double *Z1, double *Z2, void *stream) {
     double *L[2] = {L1, L2}, *Z[2] = {Z1, Z2};
-    return run(ctx, img, p, nullptr, L, Z, nullptr, stream);
+    if (!img) return set_err(ctx, LOGFX_EINVAL, "image is NULL");
+    return run(ctx, 1, img, p, nullptr, L, Z, nullptr, stream);
+}
+
+int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    switch (option) {
+    case LOGFX_OPT_ROWS1:
+    case LOGFX_OPT_ROWS2:
+        if (value < 1 || value > 1024) return set_err(ctx, LOGFX_EINVAL, "rows %lld not in 1..1024", (long long)value);
+        (option == LOGFX_OPT_ROWS1 ? ctx->tiles.rows1 : ctx->tiles.rows2) = (int)value;
+        return LOGFX_OK;
+    case LOGFX_OPT_PERSISTENT: ctx->persistent = value != 0; return LOGFX_OK;
+    case LOGFX_OPT_GRAPH: ctx->graph = value != 0; return LOGFX_OK;
+    default: return set_err(ctx, LOGFX_EINVAL, "unknown option %d", option);
+    }
+}
+
+int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value) {
+    if (!ctx || !value) return set_err(ctx, LOGFX_EINVAL, "ctx or value is NULL");
+    switch (option) {
+    case LOGFX_OPT_ROWS1: *value = ctx->tiles.rows1; return LOGFX_OK;
+    case LOGFX_OPT_ROWS2: *value = ctx->tiles.rows2; return LOGFX_OK;
+    case LOGFX_OPT_PERSISTENT: *value = ctx->persistent; return LOGFX_OK;
+    case LOGFX_OPT_GRAPH: *value = ctx->graph; return LOGFX_OK;
+    default: return set_err(ctx, LOGFX_EINVAL, "unknown option %d", option);
+    }
 }
 
 int logfx_timing_enable(logfx_ctx *ctx, int on) {
@@ -573,18 +818,23 @@ int logfx_timing_enable(logfx_ctx *ctx, int on) {
 
 int logfx_timing_read(logfx_ctx *ctx, double *ms_out, int64_t *calls_out) {
     if (!ctx || !ms_out) return set_err(ctx, LOGFX_EINVAL, "ctx or ms_out is NULL");
-    ms_out[0] = ms_out[1] = ms_out[2] = 0.0;
+    for (int k = 0; k < 4; ++k) ms_out[k] = 0.0;
     DeviceGuard dg(ctx->device);
     for (long long c = 0; c < ctx->timed_calls; ++c) {
         hipEvent_t *ev = &ctx->events[4 * c];
         hipError_t e = hipEventSynchronize(ev[3]);
         if (e != hipSuccess) return hip_err(ctx, e, "hipEventSynchronize");
-        for (int k = 0; k < 3; ++k) {
-            float ms = 0.0f;
-            if ((e = hipEventElapsedTime(&ms, ev[k], ev[k + 1])) != hipSuccess)
-                return hip_err(ctx, e, "hipEventElapsedTime");
-            ms_out[k] += ms;
+        float ms = 0.0f;
+        if (!ctx->timed_graph[c]) {
+            for (int k = 0; k < 3; ++k) {
+                if ((e = hipEventElapsedTime(&ms, ev[k], ev[k + 1])) != hipSuccess)
+                    return hip_err(ctx, e, "hipEventElapsedTime");
+                ms_out[k] += ms;
+            }
         }
+        if ((e = hipEventElapsedTime(&ms, ev[0], ev[3])) != hipSuccess)
+            return hip_err(ctx, e, "hipEventElapsedTime");
+        ms_out[3] += ms;
     }
     if (calls_out) *calls_out = ctx->timed_calls;
     ctx->timed_calls = 0;

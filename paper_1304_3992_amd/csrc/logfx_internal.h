@@ -52,18 +52,39 @@ __host__ __device__ constexpr int tile_lds_stride(int halo, int rb) {
     return (tile_out_width(halo) + 2 * halo + 2 * rb + tile_lds_offset(halo, rb) + 7) / 8 * 8;
 }
 
+// One image of a launch: its input, its output and where its tiles sit in
+// the launch's tile list.
+struct ImageJob {
+    ImageDesc img;
+    uint8_t *out;          // pass-2 output (pitch out_pitch); unused by pass 1
+    long long out_pitch;
+    int tiles_x1, tiles_x2;  // tiles across the image in pass 1 / pass 2
+    int base1, base2;        // index of the image's first tile among the launch's tiles
+    int ntiles1, ntiles2;
+};
+
+// The work of one launch: one image (passed inline) or a batch of images
+// (a device table), each cut into tiles.  A workgroup may process several
+// tiles (persistent launch) or one (grid = number of tiles).
+struct Launch {
+    int nimg;
+    ImageJob one;            // the image when nimg == 1
+    const ImageJob *jobs;    // device table of nimg images when nimg > 1
+    const int *owner1;       // [total1] image of each pass-1 tile (nimg > 1)
+    const int *owner2;       // [total2] image of each pass-2 tile (nimg > 1)
+    int total1, total2;      // tiles of all images, pass 1 / pass 2
+};
+
 template <class Taps>
 struct Pass1Args {
-    ImageDesc img;
+    Launch L;
     Taps taps;
     double zc_thr[2];      // zero-crossing threshold per mask, grid units
     int zc_thr_i[2];       // the same for integer strengths: floor, capped at INT_MAX
     int rows;              // output rows per wave strip
-    int tiles_x;           // tiles across the image (tile width = kTileWaves * (64 - 2 halo))
-    int ntiles;            // tiles in the image (= grid size)
-    double *partials;      // [ntiles][4]: sum Z1, sum Z2, sum Z1^2, sum Z2^2
-    long long *counts;     // [ntiles][2]: crossings of mask 1, mask 2
-    // Optional FP64 maps (LoG units = grid units * unit[j]); NULL to skip.
+    double *partials;      // [total1][4]: sum Z1, sum Z2, sum Z1^2, sum Z2^2 per tile
+    long long *counts;     // [total1][2]: crossings of mask 1, mask 2 per tile
+    // Optional FP64 maps of a single image (LoG units = grid units * unit[j]).
     double *dbgL[2];
     double *dbgZ[2];
     double unit[2];
@@ -71,38 +92,40 @@ struct Pass1Args {
 
 template <class Taps>
 struct Pass2Args {
-    ImageDesc img;
+    Launch L;
     Taps taps;
     double zc_thr[2];
     int zc_thr_i[2];
     int rows;
-    int tiles_x;
-    int ntiles;
-    const DevStats *stats;  // thresholds from the finalize kernel
-    uint8_t *out;           // H x W, pitch out_pitch
-    long long out_pitch;
+    const DevStats *stats;  // [nimg] thresholds from the finalize kernel
+    int *counts;            // [total2][2]: E pixels, output pixels per tile
     int smooth;             // 0 = E, 1 = hybrid median of E
     int median_size;        // 3 or 5
-    int *counts;            // [ntiles][2]: E pixels, output pixels
 };
 
 struct FinalizeArgs {
+    Launch L;
     const double *partials;
     const long long *counts;
-    int ntiles;
-    long long n;           // pixels
     int std_mode;          // 0 relative, 1 absolute
     double std_k;
     double abs_thr[2];     // absolute threshold per mask in grid units (std_mode 1)
-    DevStats *stats;
+    DevStats *stats;       // [nimg]
 };
 
 // Launchers (defined in logfx_kernels.hip).  They return hipSuccess or the
-// launch error.  ra <= rb are the radii of the two masks.
-hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, hipStream_t s);
-hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, hipStream_t s);
-hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, hipStream_t s);
-hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, hipStream_t s);
+// launch error.  ra <= rb are the radii of the two masks.  grid = number of
+// workgroups (at most the number of tiles; fewer makes the launch
+// persistent).  max_grid, when non-null, receives the number of workgroups
+// that fit on the device at once and nothing is launched.
+hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, int grid,
+                          hipStream_t s, int *max_grid = nullptr);
+hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, int grid,
+                          hipStream_t s, int *max_grid = nullptr);
+hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s,
+                          int *max_grid = nullptr);
+hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s,
+                          int *max_grid = nullptr);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
 // LDS bytes of one workgroup.

@@ -13,8 +13,8 @@
 // staged once in LDS as u16 with clamp-to-edge coordinates.  Each lane owns
 // one column and walks down the rows, keeping a ring of 2R+1 rows of
 // horizontal pair sums in registers.  Horizontal neighbours of later
-// stages come from the adjacent lanes (ds_bpermute with clamped source
-// lanes), so stage-wise clamp-to-edge borders come for free.  The extracted
+// stages come from the adjacent lanes (DPP wave shifts on the vector ALU;
+// lanes at the image border take their own value).  The extracted
 // bits of a row are a 64-bit wave ballot; the hybrid median of those bits is
 // computed bit-sliced on the scalar unit, 64 pixels per instruction.
 //
@@ -22,32 +22,40 @@
 // is evaluated on D4 orbit sums of pixels: L = sum_o k_o * O_o.  Every sum is
 // exact (int32 when sum|k| (2^bits - 1) < 2^30, else FP64 below 2^52), so L
 // and Z agree bit for bit with any exact evaluation.
+#pragma once
 #include "logfx_internal.h"
 
 #include <type_traits>
 
 namespace logfx {
-namespace {
+namespace kern {
 
 // ----------------------------------------------------------------- helpers
-__device__ inline int xcd_remap(int b, int n) {
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of tiles so neighbouring tiles (which share halo rows
-    // and columns) meet in the same L2.
-    constexpr int X = 8;
-    const int q = n / X, rem = n % X;
-    const int xcd = b % X, slot = b / X;
-    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
-}
-
 __device__ inline long long clampll(long long v, long long lo, long long hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
-__device__ inline int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
-__device__ inline double bperm(int addr, double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(bperm(addr, hi), bperm(addr, lo));
+// Values of the lanes to the left (column x - 1) and right (x + 1), by DPP
+// wave shifts on the vector ALU.  Lanes 0 and 63 keep their own value (they
+// are halo lanes whose results are never used).  At the image border the
+// neighbour is clamped to the lane itself when the tile touches a border
+// (EDGE); interior tiles skip the test.
+__device__ inline int from_left(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ inline int from_right(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ inline double from_left(double v) {
+    return __hiloint2double(from_left(__double2hiint(v)), from_left(__double2loint(v)));
+}
+__device__ inline double from_right(double v) {
+    return __hiloint2double(from_right(__double2hiint(v)), from_right(__double2loint(v)));
+}
+template <bool EDGE, class T>
+__device__ inline void neighbours(T v, bool clampL, bool clampR, T &l, T &r) {
+    l = from_left(v);
+    r = from_right(v);
+    if constexpr (EDGE) {
+        l = clampL ? v : l;
+        r = clampR ? v : r;
+    }
 }
 
 // Accumulator policies: exact int32 or exact FP64 LoG sums.
@@ -130,12 +138,6 @@ __device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr 
     if (__ballot(a == 0)) is = is | ((a == 0) & (opposite(lf, rt) | opposite(up, dn)));
     const Acc c = max(a, qmax) - min(a, qmin);   // exact: |L| < 2^30 (int) or 2^52 (FP64)
     return AccOps<Acc>::to_d((is & (c > thr)) ? c : Acc(0));
-}
-
-// Lane offset (x4, for ds_bpermute) of the clamped column col.
-__device__ inline int lane_addr(int col, int W, int base) {
-    const int c = min(max(col, 0), W - 1) - base;
-    return min(max(c, 0), kWave - 1) * 4;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -223,8 +225,8 @@ struct Strip {
     static constexpr int OFF = tile_lds_offset(HL, RB);   // LDS column of image column x0-HL-RB
     static constexpr int stride = tile_lds_stride(HL, RB);  // LDS row pitch (u16), 8-multiple
     int H, W, x0, y0, Rv, RH;
-    int lane, base, xc, lc, aL, aR;
-    bool outc;
+    int lane, base, xc, lc;
+    bool outc, clampL, clampR;   // output column; left / right neighbour is the lane itself
 
     __device__ Strip(const ImageDesc &img, int tile, int tiles_x, int rows) {
         H = (int)img.H;
@@ -241,8 +243,8 @@ struct Strip {
         base = x0 + wave * OW - HL;
         xc = base + lane;
         lc = wave * OW + lane + RB + OFF;
-        aL = lane_addr(xc - 1, W, base);
-        aR = lane_addr(xc + 1, W, base);
+        clampL = xc <= 0;
+        clampR = xc >= W - 1;
         outc = lane >= HL && lane < HL + OW && xc < W;
     }
 
@@ -319,17 +321,49 @@ __device__ inline void ring_push(T (&ring)[N], T v, int row, int H) {
 
 template <bool B> using bool_c = std::integral_constant<bool, B>;
 
+// ------------------------------------------------------------- work list
+// Tiles of a launch are split into 8 contiguous shares, one per XCD
+// (workgroups are dispatched round-robin over the XCDs), so neighbouring
+// tiles, which share halo rows and columns, meet in the same L2.  The
+// workgroups of an XCD stride through its share: one tile each when the
+// grid has one workgroup per tile, several in a persistent launch.
+// LOOP false: one workgroup per tile (grid = total), no loop in the code.
+template <bool LOOP, class F>
+__device__ inline void for_each_tile(int total, F &&f) {
+    constexpr int X = 8;
+    const int G = gridDim.x, b = blockIdx.x;
+    const int x = b % X, l = b / X;
+    const int start = x * (total / X) + min(x, total % X);
+    if constexpr (!LOOP) {
+        f(start + l);
+    } else {
+        const int len = total / X + (x < total % X);
+        const int nx = G / X + (x < G % X);
+        for (int i = l; i < len; i += nx) f(start + i);
+    }
+}
+
+__device__ inline ImageJob job_of(const Launch &L, int image) {
+    return L.nimg == 1 ? L.one : L.jobs[image];
+}
+
 // ------------------------------------------------------------- pass 1
-template <class Acc, int RA, int RB, bool DBG>
-__global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
+// Occupancy: the integer path is held to 128 VGPRs (4 waves per SIMD, the
+// LDS limit), which costs a few spills but measures faster than 3 waves; the
+// FP64 path keeps its registers.
+template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
+
+template <class Acc, int RA, int RB, bool DBG, bool LOOP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ double red[4][8];
     __shared__ long long redc[2][8];
     constexpr int HL = kHalo1, P = 2 * RB + 1;
 
-    const int tile = xcd_remap(blockIdx.x, a.ntiles);
-    const Strip<HL, RB> g(a.img, tile, a.tiles_x, a.rows);
-    g.fill(lds, a.img);
+    for_each_tile<LOOP>(a.L.total1, [&](const int item) __attribute__((always_inline)) {
+    const ImageJob J = job_of(a.L, a.L.nimg == 1 ? 0 : a.L.owner1[item]);
+    const Strip<HL, RB> g(J.img, item - J.base1, J.tiles_x1, a.rows);
+    g.fill(lds, J.img);
     __syncthreads();
 
     int h[P][RB + 1];
@@ -364,7 +398,8 @@ __global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Ac
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const Acc c = L[j][1];
-            const Acc lf = bperm(g.aL, c), rt = bperm(g.aR, c);
+            Acc lf, rt;
+            neighbours<C>(c, g.clampL, g.clampR, lf, rt);
             const double z = zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j));
             const double zu = use ? z : 0.0;
             sz[j] += zu;
@@ -387,7 +422,10 @@ __global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Ac
         }
         for (; si0 < nsteps; ++si0) step(si0, clamp);
     };
-    if (t0 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
+    // interior tile: every row and column the strip touches lies strictly
+    // inside the image, so no border test is needed
+    const bool inner_x = g.x0 - HL >= 1 && g.x0 + Strip<HL, RB>::TW + HL <= g.W - 1;
+    if (inner_x && t0 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
     else run(bool_c<true>{});
 
     // Deterministic per-tile reduction: fixed butterfly per wave, then the
@@ -412,71 +450,30 @@ __global__ __launch_bounds__(256) void pass1_kernel(Pass1Args<typename AccOps<Ac
             cc[1] += redc[1][w];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a.partials[(long long)tile * 4 + k] = s[k];
-        a.counts[(long long)tile * 2 + 0] = cc[0];
-        a.counts[(long long)tile * 2 + 1] = cc[1];
+        for (int k = 0; k < 4; ++k) a.partials[(long long)item * 4 + k] = s[k];
+        a.counts[(long long)item * 2 + 0] = cc[0];
+        a.counts[(long long)item * 2 + 1] = cc[1];
     }
-}
-
-// ------------------------------------------------------------- finalize
-__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
-    __shared__ double sd[4][256];
-    __shared__ long long sc[2][256];
-    const int t = threadIdx.x;
-    double s[4] = {0, 0, 0, 0};
-    long long c[2] = {0, 0};
-    for (int i = t; i < a.ntiles; i += 256) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] += a.partials[(long long)i * 4 + k];
-        c[0] += a.counts[(long long)i * 2];
-        c[1] += a.counts[(long long)i * 2 + 1];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sd[k][t] = s[k];
-    sc[0][t] = c[0];
-    sc[1][t] = c[1];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) sd[k][t] += sd[k][t + off];
-            sc[0][t] += sc[0][t + off];
-            sc[1][t] += sc[1][t + off];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        const double n = (double)a.n;
-        for (int j = 0; j < 2; ++j) {
-            const double S = sd[j][0], Q = sd[2 + j][0];
-            double var = a.n > 1 ? (Q - S * (S / n)) / (n - 1.0) : 0.0;
-            if (!(var > 0.0)) var = 0.0;
-            const double sg = sqrt(var);
-            const double T = a.std_mode == 0 ? a.std_k * sg : a.abs_thr[j];
-            a.stats->sum[j] = S;
-            a.stats->sumsq[j] = Q;
-            a.stats->sigma[j] = sg;
-            a.stats->thresh[j] = T;
-            a.stats->thr72[j] = 72.0 * T * T;
-            a.stats->zc[j] = sc[j][0];
-        }
-    }
+    __syncthreads();   // LDS and the reduction buffers are reused by the next tile
+    });
 }
 
 // ------------------------------------------------------------- pass 2
 // MED: 0 = no smoothing (output E), 3 or 5 = hybrid median window.
-template <class Acc, int RA, int RB, int MED>
-__global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
+template <class Acc, int RA, int RB, int MED, bool LOOP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ int redc[2][8];
     constexpr int HL = kHalo2, P = 2 * RB + 1;
 
-    const int tile = xcd_remap(blockIdx.x, a.ntiles);
-    const Strip<HL, RB> g(a.img, tile, a.tiles_x, a.rows);
-    g.fill(lds, a.img);
+    for_each_tile<LOOP>(a.L.total2, [&](const int item) __attribute__((always_inline)) {
+    const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
+    const ImageJob J = job_of(a.L, image);
+    const Strip<HL, RB> g(J.img, item - J.base2, J.tiles_x2, a.rows);
+    g.fill(lds, J.img);
     __syncthreads();
 
-    const double thr72_0 = a.stats->thr72[0], thr72_1 = a.stats->thr72[1];
+    const double thr72_0 = a.stats[image].thr72[0], thr72_1 = a.stats[image].thr72[1];
     // lanes of the first / last image column inside this wave (for the
     // bit-level clamping of the extracted map)
     const int lo_lane = g.base < 0 ? -g.base : 0;
@@ -496,9 +493,9 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
     // output row t - 4 of step si; advanced by one row per step.  The pitch
     // is moved to a vector register so the per-step offsets are not
     // materialised as scalar constants.
-    uint8_t *orow = a.out + (long long)(t0 - 4) * a.out_pitch + g.xc;
+    uint8_t *orow = J.out + (long long)(t0 - 4) * J.out_pitch + g.xc;
     long long opitch;
-    asm("v_mov_b64 %0, %1" : "=v"(opitch) : "s"(a.out_pitch));
+    asm("v_mov_b64 %0, %1" : "=v"(opitch) : "s"(J.out_pitch));
     const uint16_t *lrow = lds + (2 * RB) * g.stride + g.lc;   // LDS row of step si
 
     auto step = [&](const int si, auto clamp) __attribute__((always_inline)) {
@@ -520,7 +517,8 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
 #pragma unroll
         for (int j = 0; j < 2; ++j) {   // zero-crossing strength of row t - 1
             const Acc c = L[j][1];
-            const Acc lf = bperm(g.aL, c), rt = bperm(g.aR, c);
+            Acc lf, rt;
+            neighbours<C>(c, g.clampL, g.clampR, lf, rt);
             ring_push<C>(Z[j], zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j)),
                          t - 1, g.H);
         }
@@ -529,8 +527,11 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
         for (int j = 0; j < 2; ++j) {   // extraction of row t - 2: 3x3 deviation of Z
             const double cs = Z[j][0] + Z[j][1] + Z[j][2];
             const double cq = __fma_rn(Z[j][0], Z[j][0], __fma_rn(Z[j][1], Z[j][1], Z[j][2] * Z[j][2]));
-            const double S = bperm(g.aL, cs) + cs + bperm(g.aR, cs);
-            const double Q = bperm(g.aL, cq) + cq + bperm(g.aR, cq);
+            double csl, csr, cql, cqr;
+            neighbours<C>(cs, g.clampL, g.clampR, csl, csr);
+            neighbours<C>(cq, g.clampL, g.clampR, cql, cqr);
+            const double S = csl + cs + csr;
+            const double Q = cql + cq + cqr;
             // 9 sum z^2 - (sum z)^2 = 72 s^2 for the unbiased s of eq. (2)
             const double V = __fma_rn(-S, S, 9.0 * Q);
             ej = ej || (V > (j == 0 ? thr72_0 : thr72_1));
@@ -556,8 +557,10 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
         }
         for (; si0 < nsteps; ++si0) step(si0, clamp);
     };
-    // rows t-2 .. t of every step stay inside the image: no clamping needed
-    if (t0 - 2 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
+    // interior tile: rows t-2 .. t of every step and every column of the
+    // strip lie strictly inside the image, so no border test is needed
+    const bool inner_x = g.x0 - HL >= 1 && g.x0 + Strip<HL, RB>::TW + HL <= g.W - 1;
+    if (inner_x && t0 - 2 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
     else run(bool_c<true>{});
 
     const int wave = threadIdx.x / kWave;
@@ -572,67 +575,64 @@ __global__ __launch_bounds__(256) void pass2_kernel(Pass2Args<typename AccOps<Ac
             s0 += redc[0][w];
             s1 += redc[1][w];
         }
-        a.counts[(long long)tile * 2] = s0;
-        a.counts[(long long)tile * 2 + 1] = s1;
+        a.counts[(long long)item * 2] = s0;
+        a.counts[(long long)item * 2 + 1] = s1;
     }
+    __syncthreads();   // LDS and the reduction buffers are reused by the next tile
+    });
 }
 
-// ------------------------------------------------------------- dispatch
+// ------------------------------------------------------------- launch templates
+// Workgroups of kernel k that fit on the device at once.
+template <class K>
+hipError_t occupancy(K k, size_t shm, int *max_grid) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTileWaves * kWave, shm);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) *max_grid = per_cu * cus;
+    return e;
+}
+
 template <class Acc, int RA, int RB, bool DBG>
-hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
+hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
     const size_t shm = lds_bytes(a.rows, kHalo1, RB);
-    hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG>), dim3(a.ntiles), dim3(kTileWaves * kWave), shm,
-                       s, a);
+    // the map-writing variant is for single images only: always one tile
+    // per workgroup
+    if constexpr (DBG) {
+        if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, DBG, false>, shm, max_grid);
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG, false>), dim3(a.L.total1),
+                           dim3(kTileWaves * kWave), shm, s, a);
+        return hipGetLastError();
+    }
+    if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, DBG, true>, shm, max_grid);
+    if (grid >= a.L.total1)
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG, false>), dim3(a.L.total1),
+                           dim3(kTileWaves * kWave), shm, s, a);
+    else
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG, true>), dim3(grid),
+                           dim3(kTileWaves * kWave), shm, s, a);
+    return hipGetLastError();
+}
+
+template <class Acc, int RA, int RB, int MED>
+hipError_t p2m(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
+    const size_t shm = lds_bytes(a.rows, kHalo2, RB);
+    if (max_grid) return occupancy(pass2_kernel<Acc, RA, RB, MED, true>, shm, max_grid);
+    if (grid >= a.L.total2)
+        hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, false>), dim3(a.L.total2),
+                           dim3(kTileWaves * kWave), shm, s, a);
+    else
+        hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, true>), dim3(grid),
+                           dim3(kTileWaves * kWave), shm, s, a);
     return hipGetLastError();
 }
 template <class Acc, int RA, int RB>
-hipError_t p2(const Pass2Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
-    const size_t shm = lds_bytes(a.rows, kHalo2, RB);
-    const dim3 g(a.ntiles), b(kTileWaves * kWave);
-    if (!a.smooth) hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, 0>), g, b, shm, s, a);
-    else if (a.median_size == 3) hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, 3>), g, b, shm, s, a);
-    else hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, 5>), g, b, shm, s, a);
-    return hipGetLastError();
+hipError_t p2(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
+    if (!a.smooth) return p2m<Acc, RA, RB, 0>(a, grid, s, max_grid);
+    if (a.median_size == 3) return p2m<Acc, RA, RB, 3>(a, grid, s, max_grid);
+    return p2m<Acc, RA, RB, 5>(a, grid, s, max_grid);
 }
 
-#define LOGFX_RADII(X)                                                                            \
-    X(1, 1) X(1, 2) X(2, 2) X(1, 3) X(2, 3) X(3, 3) X(1, 4) X(2, 4) X(3, 4) X(4, 4)
-
-template <class Acc>
-hipError_t dispatch1(int ra, int rb, const Pass1Args<typename AccOps<Acc>::Taps> &a, bool dbg,
-                     hipStream_t s) {
-#define X(A, B)                                                                                   \
-    if (ra == A && rb == B) return dbg ? p1<Acc, A, B, true>(a, s) : p1<Acc, A, B, false>(a, s);
-    LOGFX_RADII(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-template <class Acc>
-hipError_t dispatch2(int ra, int rb, const Pass2Args<typename AccOps<Acc>::Taps> &a, hipStream_t s) {
-#define X(A, B)                                                                                   \
-    if (ra == A && rb == B) return p2<Acc, A, B>(a, s);
-    LOGFX_RADII(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
-
-hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, hipStream_t s) {
-    return dispatch1<int>(ra, rb, a, dbg, s);
-}
-hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, hipStream_t s) {
-    return dispatch1<double>(ra, rb, a, dbg, s);
-}
-hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, hipStream_t s) {
-    return dispatch2<int>(ra, rb, a, s);
-}
-hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, hipStream_t s) {
-    return dispatch2<double>(ra, rb, a, s);
-}
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
+}  // namespace kern
 }  // namespace logfx

@@ -23,7 +23,9 @@ PATH_INT32, PATH_FP64 = 0, 1
 
 EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_make_log_mask", "logfx_check_params", "logfx_extract", "logfx_extract_maps",
-           "logfx_timing_enable", "logfx_timing_read"]
+           "logfx_timing_enable", "logfx_timing_read", "logfx_extract_batch",
+           "logfx_set_option", "logfx_get_option"]
+OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH = 1, 2, 3, 4
 
 
 class LogfxError(RuntimeError):
@@ -99,6 +101,14 @@ def load(path: str | None = None):
     lib.logfx_extract_maps.restype = ctypes.c_int
     lib.logfx_extract_maps.argtypes = [P, ctypes.POINTER(logfx_image),
                                        ctypes.POINTER(logfx_params), P, P, P, P, P]
+    lib.logfx_extract_batch.restype = ctypes.c_int
+    lib.logfx_extract_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(logfx_image),
+                                        ctypes.POINTER(logfx_params), ctypes.POINTER(P),
+                                        ctypes.POINTER(logfx_report), P]
+    lib.logfx_set_option.restype = ctypes.c_int
+    lib.logfx_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
+    lib.logfx_get_option.restype = ctypes.c_int
+    lib.logfx_get_option.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
     lib.logfx_timing_enable.restype = ctypes.c_int
     lib.logfx_timing_enable.argtypes = [P, ctypes.c_int]
     lib.logfx_timing_read.restype = ctypes.c_int
@@ -235,12 +245,36 @@ class Context:
         _check(self.lib.logfx_timing_enable(self.ptr, int(bool(on))), self.ptr)
 
     def timing_read(self):
-        """Summed kernel milliseconds (pass 1, finalize, pass 2) and the
+        """Summed milliseconds (pass 1, finalize, pass 2, whole call) and the
         number of timed calls since the last read."""
-        ms = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * 4)()
         calls = ctypes.c_int64(0)
         _check(self.lib.logfx_timing_read(self.ptr, ms, ctypes.byref(calls)), self.ptr)
         return list(ms), calls.value
+
+    def set_option(self, option: int, value: int):
+        _check(self.lib.logfx_set_option(self.ptr, option, int(value)), self.ptr)
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64(0)
+        _check(self.lib.logfx_get_option(self.ptr, option, ctypes.byref(v)), self.ptr)
+        return v.value
+
+    def extract_batch(self, imgs, params: Params, outs=None, *, bits: int = 0,
+                      report: bool = False, stream=None):
+        """logfx_extract_batch on a list of device tensors; returns the list of
+        uint8 maps (and the list of report dicts when ``report``)."""
+        import torch
+        n = len(imgs)
+        descs = (logfx_image * n)(*[image(t, bits) for t in imgs])
+        if outs is None:
+            outs = [torch.empty(t.shape, dtype=torch.uint8, device=t.device) for t in imgs]
+        ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        reps = (logfx_report * n)() if report else None
+        rc = self.lib.logfx_extract_batch(self.ptr, n, descs, ctypes.byref(params.c), ptrs,
+                                          reps, _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return (outs, [r.as_dict() for r in reps]) if report else outs
 
     def extract_maps(self, img_t, params: Params, *, bits: int = 0, want=("L1", "L2", "Z1", "Z2"),
                      stream=None):

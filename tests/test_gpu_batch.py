@@ -1,0 +1,135 @@
+"""GPU parity of the batched form (logfx_extract_batch): many uneven tiles in
+one launch per pass, persistent or not, replayed from a hipGraph or not.
+Every tile is an independent image: its map must equal the single-image
+call bit for bit, and the oracle under the band rule."""
+import numpy as np
+import pytest
+
+from paper_1304_3992_amd import logfx, scenes
+from parity import compare, masks, run_oracle, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = logfx.Context(0)
+    yield c
+    c.close()
+
+
+def _tiles(n=9, seed=31, lo=40, hi=700):
+    return scenes.config3(n=n, seed=seed, base_seed=5000 + seed, lo=lo, hi=hi)
+
+
+def _singles(ctx, devs, params):
+    return [ctx.extract(t, params, report=True) for t in devs]
+
+
+@pytest.mark.parametrize("persistent,graph", [(1, 1), (0, 1), (1, 0), (0, 0)])
+def test_batch_equals_single_calls_and_oracle(ctx, persistent, graph):
+    import torch
+    tiles = _tiles()
+    orc_t, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    devs = [to_device(t) for t in tiles]
+    ctx.set_option(logfx.OPT_PERSISTENT, persistent)
+    ctx.set_option(logfx.OPT_GRAPH, graph)
+    try:
+        outs, reps = ctx.extract_batch(devs, params, report=True)
+    finally:
+        ctx.set_option(logfx.OPT_PERSISTENT, 1)
+        ctx.set_option(logfx.OPT_GRAPH, 1)
+    torch.cuda.synchronize()
+    singles = _singles(ctx, devs, params)
+    torch.cuda.synchronize()
+    for i, t in enumerate(tiles):
+        F = outs[i].cpu().numpy()
+        Fs, rs = singles[i]
+        assert np.array_equal(F, Fs.cpu().numpy()), i
+        assert reps[i] == rs, i
+        compare(F, run_oracle(t, orc_t), smooth=True)
+
+
+def test_graph_replays_match_eager(ctx):
+    """The captured graph is replayed several times with eager work and
+    synchronisations in between; every replay must equal the eager result,
+    including after new input data in the same buffers."""
+    import torch
+    tiles = _tiles(n=6, seed=32)
+    _, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    devs = [to_device(t) for t in tiles]
+    outs = [torch.empty(t.shape, dtype=torch.uint8, device="cuda") for t in tiles]
+    ctx.set_option(logfx.OPT_GRAPH, 0)
+    eager = [o.clone() for o in ctx.extract_batch(devs, params)]
+    ctx.set_option(logfx.OPT_GRAPH, 1)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(7)
+        ctx.extract_batch(devs, params, outs)
+        torch.cuda.synchronize()
+        junk = torch.ones(1 << 20, device="cuda").sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+        del junk
+    # new pixels in the same buffers: the replay must pick them up
+    flipped = [np.ascontiguousarray(t[::-1]) for t in tiles]
+    for d, f in zip(devs, flipped):
+        d.copy_(to_device(f))
+    ctx.extract_batch(devs, params, outs)
+    ctx.set_option(logfx.OPT_GRAPH, 0)
+    ref = ctx.extract_batch(devs, params)
+    ctx.set_option(logfx.OPT_GRAPH, 1)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
+
+
+def test_batch_rejects_mixed_dtypes(ctx):
+    _, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    a = to_device(np.zeros((20, 20), np.uint8))
+    b = to_device(np.zeros((20, 20), np.uint16))
+    with pytest.raises(logfx.LogfxError) as e:
+        ctx.extract_batch([a, b], params)
+    assert e.value.code == logfx.EINVAL
+
+
+def test_batch_edge_shapes(ctx):
+    """Degenerate members of a batch: a single pixel, one row, one column,
+    and a tile narrower than the halo, next to an ordinary tile."""
+    import torch
+    rng = np.random.default_rng(33)
+    tiles = [np.array([[5]], np.uint16), rng.integers(0, 256, (1, 300)).astype(np.uint16),
+             rng.integers(0, 256, (300, 1)).astype(np.uint16),
+             rng.integers(0, 256, (3, 7)).astype(np.uint16),
+             scenes.config3(n=1, seed=34, lo=300, hi=400)[0]]
+    orc_t, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    outs = ctx.extract_batch([to_device(t) for t in tiles], params)
+    torch.cuda.synchronize()
+    for t, o in zip(tiles, outs):
+        compare(o.cpu().numpy(), run_oracle(t, orc_t), smooth=True)
+
+
+def test_config3_full_batch(ctx):
+    """The 64 uneven tiles (sides log-uniform in [256, 4096]) in one call at
+    the benchmark's launch configuration, each against the oracle."""
+    import torch
+    tiles = scenes.config3()
+    orc_t, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    outs, reps = ctx.extract_batch([to_device(t) for t in tiles], params, report=True)
+    torch.cuda.synchronize()
+    total = 0
+    for t, o, r in zip(tiles, outs, reps):
+        o_ref = run_oracle(t, orc_t)
+        compare(o.cpu().numpy(), o_ref, smooth=True)
+        np.testing.assert_allclose(r["sigma_g"], o_ref["stats"][:2], rtol=1e-12)
+        total += t.size
+    assert total > 50_000_000
