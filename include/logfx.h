@@ -187,6 +187,26 @@ enum {
 int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value);
 int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value);
 
+/* Autotuner (the launch-parameter sweep of Table 4, Sec. 6.2.3, made
+ * automatic).  Runs the given call (one image, or a batch when n > 1) with
+ * each candidate strip height for pass 1 and pass 2 (32, 48, 64, 96 rows,
+ * as far as they fit in LDS) and, for batches, with and without the
+ * persistent launch, `reps` timed repetitions each, and keeps the fastest
+ * in the context (LOGFX_OPT_ROWS1/ROWS2/PERSISTENT).  The outputs are
+ * written as by the call itself.  cache_path (nullable): a text file of
+ * JSON lines keyed by device architecture, arithmetic path, mask radii,
+ * pixel type, smoothing and batch/single; an entry found there is applied
+ * without measuring, a new result is appended.  res (nullable) receives the
+ * choice. */
+typedef struct {
+    int32_t rows1, rows2, persistent;
+    int32_t from_cache;   /* 1 if taken from the cache file */
+    double ms;            /* milliseconds of one call with the choice */
+} logfx_tune_result;
+int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
+               uint8_t *const *outs, int32_t reps, const char *cache_path, logfx_tune_result *res,
+               void *stream);
+
 /* Kernel timing (the split of Table 6 in Sec. 7 between transfers and
  * kernel time, refined per kernel).  While enabled, every extract call on
  * the context records HIP events around its kernels on the call's stream.

@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -658,6 +660,55 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
     return LOGFX_OK;
 }
 
+
+// ------------------------------------------------------------ autotuner
+// Key of a tuned configuration: device architecture, arithmetic path, mask
+// radii, pixel type, smoothing and whether the call is a batch.
+std::string tune_key(logfx_ctx *ctx, const Call &c, const logfx_params *p, const logfx_image *img0) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+    }
+    std::ostringstream k;
+    k << arch << "|" << (c.pl.path == LOGFX_PATH_INT32 ? "int32" : "fp64") << "|r" << c.pl.ra << c.pl.rb
+      << "|" << (img0->dtype == LOGFX_U8 ? "u8" : "u16") << "|med"
+      << (p->smooth == LOGFX_SMOOTH_ALWAYS ? p->median_size : 0) << "|" << (c.n > 1 ? "batch" : "single");
+    return k.str();
+}
+
+// The cache is a text file of JSON objects, one per line:
+// {"key": "...", "rows1": R1, "rows2": R2, "persistent": P, "ms": T}
+bool cache_lookup(const char *path, const std::string &key, logfx_tune_result &r) {
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const std::string tag = "\"key\": \"" + key + "\"";
+        if (line.find(tag) == std::string::npos) continue;
+        int r1, r2, pe;
+        double ms;
+        const size_t at = line.find("\"rows1\"");
+        if (at == std::string::npos) continue;
+        if (std::sscanf(line.c_str() + at, "\"rows1\": %d, \"rows2\": %d, \"persistent\": %d, \"ms\": %lf",
+                        &r1, &r2, &pe, &ms) == 4) {
+            r.rows1 = r1, r.rows2 = r2, r.persistent = pe, r.ms = ms;
+            found = true;   // the last entry for a key wins
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const logfx_tune_result &r) {
+    std::ofstream f(path, std::ios::app);
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "{\"key\": \"%s\", \"rows1\": %d, \"rows2\": %d, \"persistent\": %d, \"ms\": %.6f}\n",
+                  key.c_str(), r.rows1, r.rows2, r.persistent, r.ms);
+    f << buf;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -838,6 +889,81 @@ int logfx_timing_read(logfx_ctx *ctx, double *ms_out, int64_t *calls_out) {
     }
     if (calls_out) *calls_out = ctx->timed_calls;
     ctx->timed_calls = 0;
+    return LOGFX_OK;
+}
+
+int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
+               uint8_t *const *outs, int32_t reps, const char *cache_path, logfx_tune_result *res,
+               void *stream) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    if (reps < 1 || reps > 1000) return set_err(ctx, LOGFX_EINVAL, "reps %d not in 1..1000", reps);
+    ctx->err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(ctx->device);
+    Call c;
+    int rc = prepare(ctx, n, imgs, p, outs, true, c, s);
+    if (rc != LOGFX_OK) return rc;
+    const std::string key = tune_key(ctx, c, p, &imgs[0]);
+    logfx_tune_result best;
+    std::memset(&best, 0, sizeof best);
+    if (cache_path && cache_lookup(cache_path, key, best)) {
+        best.from_cache = 1;
+    } else {
+        const TileCfg saved = ctx->tiles;
+        const bool saved_p = ctx->persistent, saved_g = ctx->graph, saved_t = ctx->timing;
+        ctx->graph = false;   // direct launches, so that each kernel is timed on its own
+        const int cand[] = {32, 48, 64, 96};
+        // time one configuration: the sums of pass-1, pass-2 and whole-call milliseconds
+        auto measure = [&](double ms[4]) -> int {
+            int r;
+            if ((r = run(ctx, n, imgs, p, outs, nullptr, nullptr, nullptr, stream)) != LOGFX_OK) return r;
+            ctx->timing = true;
+            ctx->timed_calls = 0;
+            for (int i = 0; i < reps; ++i)
+                if ((r = run(ctx, n, imgs, p, outs, nullptr, nullptr, nullptr, stream)) != LOGFX_OK) return r;
+            int64_t calls;
+            return logfx_timing_read(ctx, ms, &calls);
+        };
+        double best1 = 1e300, best2 = 1e300;
+        int r1 = saved.rows1, r2 = saved.rows2;
+        for (int rows : cand) {
+            if (lds_bytes(rows, kHalo1, c.pl.rb) > 65536 && lds_bytes(rows, kHalo2, c.pl.rb) > 65536) continue;
+            ctx->tiles.rows1 = lds_bytes(rows, kHalo1, c.pl.rb) <= 65536 ? rows : saved.rows1;
+            ctx->tiles.rows2 = lds_bytes(rows, kHalo2, c.pl.rb) <= 65536 ? rows : saved.rows2;
+            double ms[4];
+            if ((rc = measure(ms)) != LOGFX_OK) break;
+            if (ctx->tiles.rows1 == rows && ms[0] < best1) best1 = ms[0], r1 = rows;
+            if (ctx->tiles.rows2 == rows && ms[2] < best2) best2 = ms[2], r2 = rows;
+        }
+        ctx->tiles.rows1 = r1;
+        ctx->tiles.rows2 = r2;
+        int pe = 0;
+        double bestms = 0.0;
+        if (rc == LOGFX_OK) {
+            double ms[4];
+            ctx->persistent = false;
+            if ((rc = measure(ms)) == LOGFX_OK) bestms = ms[3];
+            if (rc == LOGFX_OK && n > 1) {
+                ctx->persistent = true;
+                if ((rc = measure(ms)) == LOGFX_OK && ms[3] < bestms) bestms = ms[3], pe = 1;
+            }
+        }
+        ctx->timing = saved_t;
+        ctx->timed_calls = 0;
+        ctx->graph = saved_g;
+        ctx->persistent = saved_p;
+        if (rc != LOGFX_OK) {
+            ctx->tiles = saved;
+            return rc;
+        }
+        best.rows1 = r1, best.rows2 = r2, best.persistent = pe, best.ms = bestms / reps;
+        best.from_cache = 0;
+        if (cache_path) cache_store(cache_path, key, best);
+    }
+    ctx->tiles.rows1 = best.rows1;
+    ctx->tiles.rows2 = best.rows2;
+    ctx->persistent = best.persistent != 0;
+    if (res) *res = best;
     return LOGFX_OK;
 }
 

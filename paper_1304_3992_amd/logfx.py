@@ -24,7 +24,7 @@ PATH_INT32, PATH_FP64 = 0, 1
 EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_make_log_mask", "logfx_check_params", "logfx_extract", "logfx_extract_maps",
            "logfx_timing_enable", "logfx_timing_read", "logfx_extract_batch",
-           "logfx_set_option", "logfx_get_option"]
+           "logfx_set_option", "logfx_get_option", "logfx_tune"]
 OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH = 1, 2, 3, 4
 
 
@@ -48,6 +48,12 @@ class logfx_params(ctypes.Structure):
                 ("std_mode", ctypes.c_int32), ("std_k", ctypes.c_double),
                 ("std5_max", ctypes.c_double), ("smooth", ctypes.c_int32),
                 ("median_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class logfx_tune_result(ctypes.Structure):
+    _fields_ = [("rows1", ctypes.c_int32), ("rows2", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class logfx_report(ctypes.Structure):
@@ -109,6 +115,10 @@ def load(path: str | None = None):
     lib.logfx_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
     lib.logfx_get_option.restype = ctypes.c_int
     lib.logfx_get_option.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    lib.logfx_tune.restype = ctypes.c_int
+    lib.logfx_tune.argtypes = [P, ctypes.c_int32, ctypes.POINTER(logfx_image),
+                               ctypes.POINTER(logfx_params), ctypes.POINTER(P), ctypes.c_int32,
+                               ctypes.c_char_p, ctypes.POINTER(logfx_tune_result), P]
     lib.logfx_timing_enable.restype = ctypes.c_int
     lib.logfx_timing_enable.argtypes = [P, ctypes.c_int]
     lib.logfx_timing_read.restype = ctypes.c_int
@@ -275,6 +285,24 @@ class Context:
                                           reps, _stream_ptr(stream))
         _check(rc, self.ptr)
         return (outs, [r.as_dict() for r in reps]) if report else outs
+
+    def tune(self, imgs, params: Params, outs=None, *, bits: int = 0, reps: int = 5,
+             cache: str | None = None, stream=None) -> dict:
+        """logfx_tune for one image (a tensor) or a batch (a list of tensors)."""
+        import torch
+        imgs = list(imgs) if isinstance(imgs, (list, tuple)) else [imgs]
+        n = len(imgs)
+        descs = (logfx_image * n)(*[image(t, bits) for t in imgs])
+        if outs is None:
+            outs = [torch.empty(t.shape, dtype=torch.uint8, device=t.device) for t in imgs]
+        ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        res = logfx_tune_result()
+        rc = self.lib.logfx_tune(self.ptr, n, descs, ctypes.byref(params.c), ptrs, reps,
+                                 cache.encode() if cache else None, ctypes.byref(res),
+                                 _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return {"rows1": res.rows1, "rows2": res.rows2, "persistent": res.persistent,
+                "from_cache": res.from_cache, "ms": res.ms}
 
     def extract_maps(self, img_t, params: Params, *, bits: int = 0, want=("L1", "L2", "Z1", "Z2"),
                      stream=None):

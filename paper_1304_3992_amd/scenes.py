@@ -147,5 +147,21 @@ def config3(n: int = 64, seed: int = 3, base_seed: int = 3000, lo: int = 256, hi
     return tiles
 
 
+def gate_tile(index: int, size: int = 512, base_seed: int = 400000):
+    """One training tile of the smoothing gate and its noise-free twin: the
+    8192^2 generator's density of rectangles and polylines on a size^2 11-bit
+    tile, Gaussian noise sigma ~ U[0, 20] and salt-and-pepper density
+    ~ U[0, 0.2].  Returns (noisy, clean, sigma, density)."""
+    rng = np.random.default_rng(base_seed + index)
+    sigma = float(rng.uniform(0.0, 20.0))
+    density = float(rng.uniform(0.0, 0.2))
+    scale = size * size / float(8192 * 8192)
+    kw = dict(n_rect=max(1, round(20000 * scale)), n_poly=max(1, round(500 * scale)), bits=11)
+    seed = base_seed + 1_000_000 + index
+    noisy = panchromatic(size, size, seed, noise_sigma=sigma, sp_density=density, **kw)
+    clean = panchromatic(size, size, seed, noise_sigma=0.0, sp_density=0.0, **kw)
+    return noisy, clean, sigma, density
+
+
 def sha256(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()

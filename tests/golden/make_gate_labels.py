@@ -1,0 +1,53 @@
+"""Writes tests/golden/gate_labels.npz: the oracle's smoothing labels of the
+gate's training tiles (scenes.gate_tile).  Calls only oracle/ and scenes.
+
+Per tile (the reading of the benchmark's labelling rule): E_noisy and
+F_noisy are the oracle's unsmoothed and hybrid-median maps of the noisy tile,
+E_clean the unsmoothed map of its noise-free twin;
+D_raw = mean(E_noisy != E_clean), D_med = mean(F_noisy != E_clean), and the
+label is 1 when the median reduces the disagreement by more than 1 %
+(relative): D_med < 0.99 D_raw.  D_raw = 0 gives label 0.
+
+Run: python tests/golden/make_gate_labels.py [count] [size]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_1304_3992_amd import scenes  # noqa: E402
+
+
+def label_tile(i, size, taps):
+    noisy, clean, sigma, density = scenes.gate_tile(i, size)
+    o = oracle.extract(noisy, taps[0], taps[1], smooth=True, want_intermediates=True)
+    c = oracle.extract(clean, taps[0], taps[1], smooth=False)
+    d_raw = float((o["E"] != c["F"]).mean())
+    d_med = float((o["F"] != c["F"]).mean())
+    return d_raw, d_med, int(d_raw > 0 and d_med < 0.99 * d_raw), sigma, density
+
+
+def main():
+    count = int(sys.argv[1]) if len(sys.argv) > 1 else 20000
+    size = int(sys.argv[2]) if len(sys.argv) > 2 else 512
+    taps = (oracle.log_mask(5, 0.8, 16)[0], oracle.log_mask(9, 1.4, 16)[0])
+    rows = []
+    t0 = time.time()
+    for i in range(count):
+        rows.append(label_tile(i, size, taps))
+        if (i + 1) % 500 == 0:
+            print(f"{i + 1}/{count} tiles, {time.time() - t0:.0f} s", flush=True)
+    a = np.array(rows, dtype=np.float64)
+    np.savez_compressed(os.path.join(HERE, "gate_labels.npz"), d_raw=a[:, 0].astype(np.float32),
+                        d_med=a[:, 1].astype(np.float32), label=a[:, 2].astype(np.uint8),
+                        sigma=a[:, 3].astype(np.float32), density=a[:, 4].astype(np.float32),
+                        size=np.int32(size), count=np.int32(count))
+
+
+if __name__ == "__main__":
+    main()

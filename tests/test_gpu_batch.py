@@ -41,7 +41,7 @@ def test_batch_equals_single_calls_and_oracle(ctx, persistent, graph):
     try:
         outs, reps = ctx.extract_batch(devs, params, report=True)
     finally:
-        ctx.set_option(logfx.OPT_PERSISTENT, 1)
+        ctx.set_option(logfx.OPT_PERSISTENT, 0)
         ctx.set_option(logfx.OPT_GRAPH, 1)
     torch.cuda.synchronize()
     singles = _singles(ctx, devs, params)
@@ -133,3 +133,37 @@ def test_config3_full_batch(ctx):
         np.testing.assert_allclose(r["sigma_g"], o_ref["stats"][:2], rtol=1e-12)
         total += t.size
     assert total > 50_000_000
+
+
+def test_autotuner_choice_cache_and_unchanged_output(tmp_path):
+    """The tuner picks strip heights among its candidates, keeps the outputs
+    bit-identical, writes its cache, and a second context takes the choice
+    from the cache without measuring."""
+    import torch
+    img = scenes.panchromatic(900, 1300, 41, n_rect=150, noise_sigma=4.0)
+    _, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    dev = to_device(img)
+    cache = str(tmp_path / "tune.jsonl")
+    with logfx.Context(0) as c1:
+        ref = c1.extract(dev, params).clone()
+        res = c1.tune(dev, params, reps=2, cache=cache)
+        assert res["from_cache"] == 0
+        assert res["rows1"] in (32, 48, 64, 96) and res["rows2"] in (32, 48, 64, 96)
+        assert c1.get_option(logfx.OPT_ROWS1) == res["rows1"]
+        assert torch.equal(c1.extract(dev, params), ref)
+    with logfx.Context(0) as c2:
+        res2 = c2.tune(dev, params, reps=2, cache=cache)
+        assert res2["from_cache"] == 1
+        assert (res2["rows1"], res2["rows2"]) == (res["rows1"], res["rows2"])
+        assert torch.equal(c2.extract(dev, params), ref)
+    tiles = _tiles(n=5, seed=42)
+    devs = [to_device(t) for t in tiles]
+    with logfx.Context(0) as c3:
+        refs = [o.clone() for o in c3.extract_batch(devs, params)]
+        resb = c3.tune(devs, params, reps=2, cache=cache)
+        assert resb["persistent"] in (0, 1)
+        outs = c3.extract_batch(devs, params)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r)
