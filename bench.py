@@ -13,6 +13,14 @@ deviation and the 5x5 hybrid median.  Three copies of the input are rotated
 so the 256 MB last-level cache cannot serve a step from the previous one.
 
 Prints one JSON line (see the keys below).  Progress goes to stderr.
+
+--workload gated: the smoothing gate's workload instead -- four 16384^2
+11-bit bands cut into 256 tiles of 2048^2, each tile with its own noise,
+run as one batch per step with the gate choosing the median per tile
+(SMOOTH_GATE, parameters from paper_1304_3992_amd/gate_weights.bin), next to
+the same batch always smoothed and never smoothed; the agreement of each
+output with the oracle's best-choice output is computed from the stored
+oracle labels (tests/golden/config5_labels.npz).
 """
 from __future__ import annotations
 
@@ -93,6 +101,104 @@ def cpu_baseline(img, orc_taps, min_seconds: float = 10.0):
             "sample": f"whole {img.shape[0]}x{img.shape[1]} scene, {runs} runs, {dt:.1f} s"}
 
 
+def _c5_tile(args):
+    import numpy as np
+    from paper_1304_3992_amd import scenes
+    b, ty, tx = args
+    return scenes.config5_tile(_C5_BASE, b, ty, tx)[0]
+
+
+_C5_BASE = None
+
+
+def bench_gated(args):
+    """The four-band 16384^2 workload in 2048^2 tiles: gated vs always vs never."""
+    import multiprocessing as mp
+    import numpy as np
+    from paper_1304_3992_amd import scenes
+    global _C5_BASE
+    root = os.path.dirname(os.path.abspath(__file__))
+    t0 = time.time()
+    _C5_BASE = scenes.config5_base()
+    index = scenes.config5_index()
+    log(f"base scene {time.time() - t0:.0f} s; generating {len(index)} tiles ...")
+    # worker processes are forked before anything touches the GPU
+    with mp.get_context("fork").Pool(host_cores()) as pool:
+        tiles = pool.map(_c5_tile, index, chunksize=4)
+    _C5_BASE = None
+    log(f"tiles ready ({time.time() - t0:.0f} s)")
+    import torch
+    from paper_1304_3992_amd import logfx
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    lib_taps = (logfx.make_log_mask(5, 0.8, 16)[0], logfx.make_log_mask(9, 1.4, 16)[0])
+    modes = {"gated": logfx.SMOOTH_GATE, "always": logfx.SMOOTH_ALWAYS, "never": logfx.SMOOTH_NEVER}
+    devs = [torch.from_numpy(t.view(np.int16)).cuda() for t in tiles]
+    outs = [torch.empty(t.shape, dtype=torch.uint8, device="cuda") for t in tiles]
+    px = sum(t.size for t in tiles)
+    del tiles
+    ctx = logfx.Context(0)
+    ctx.gate_load(os.path.join(root, "paper_1304_3992_amd", "gate_weights.bin"))
+    stream = torch.cuda.current_stream()
+    res = {}
+    decisions = None
+    for name, mode in modes.items():
+        params = logfx.Params(*lib_taps, smooth=mode)
+        _, reps = ctx.extract_batch(devs, params, outs, bits=11, report=True)
+        if name == "gated":
+            decisions = np.array([r["smoothed"] for r in reps], np.int64)
+        for _ in range(args.warmup):
+            ctx.extract_batch(devs, params, outs, bits=11)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            ctx.extract_batch(devs, params, outs, bits=11)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.steps
+        res[name] = {"ms_per_step": round(ms, 4), "Mpixel_s": round(px / (ms * 1e-3) / 1e6, 1)}
+        log(f"{name}: {ms:.3f} ms/step")
+    # the gate alone (features + network + decisions)
+    params = logfx.Params(*lib_taps, smooth=logfx.SMOOTH_GATE)
+    for _ in range(args.warmup):
+        ctx.gate(devs, params, bits=11)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        ctx.gate(devs, params, bits=11)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    res["gate_only_ms"] = round(start.elapsed_time(stop) / args.steps, 4)
+    ctx.close()
+    agreement = None
+    lab_path = os.path.join(root, "tests", "golden", "config5_labels.npz")
+    if os.path.exists(lab_path):
+        d = np.load(lab_path)
+        lab, diff = d["label"].astype(np.int64), d["diff"].astype(np.float64)
+        if len(lab) == len(decisions):
+            def agree(dec):
+                return float(1.0 - diff[dec != lab].sum() / px)
+            agreement = {"gated": agree(decisions), "always": agree(np.ones_like(lab)),
+                         "never": agree(np.zeros_like(lab)),
+                         "decision_accuracy": float((decisions == lab).mean()),
+                         "smoothed_tiles": int(decisions.sum()), "best_smoothed_tiles": int(lab.sum())}
+    ms = res["gated"]["ms_per_step"]
+    result = {
+        "metric": METRIC, "value": res["gated"]["Mpixel_s"], "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "4 bands x 16384^2 uint16 11-bit (gains 0.9/1.0/1.1/0.7, offsets "
+                               "0/40/-40/80), 256 tiles of 2048^2 with per-tile noise sigma~U[0,20], "
+                               "salt-and-pepper~U[0,0.2]; gated hybrid median",
+                   "pixels": px, "tiles": len(devs), "parallelism": "single GPU"},
+        "modes": res, "agreement_with_best_choice": agreement,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (strip heights stay at their defaults)")
+    ap.add_argument("--workload", choices=["scene", "gated"], default="scene",
+                    help="scene: the 8192^2 scene (default); gated: the gate's four-band workload")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -111,6 +219,8 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; the pipeline is "
                                    "measured on a single MI355X", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "gated":
+        return bench_gated(args)
 
     import numpy as np
     import torch

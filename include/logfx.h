@@ -45,7 +45,11 @@ typedef enum {
 
 enum { LOGFX_U8 = 0, LOGFX_U16 = 1 };
 enum { LOGFX_STD_REL = 0, LOGFX_STD_ABS = 1 };
-enum { LOGFX_SMOOTH_NEVER = 0, LOGFX_SMOOTH_ALWAYS = 1 };
+/* Smoothing choice (params.smooth).  GATE: the smoothing gate (a small CNN,
+ * see logfx_gate below) decides per image whether the hybrid median is
+ * applied; with no gate parameters loaded in the context it falls back to
+ * ALWAYS and the report says so. */
+enum { LOGFX_SMOOTH_NEVER = 0, LOGFX_SMOOTH_ALWAYS = 1, LOGFX_SMOOTH_GATE = 2 };
 /* Arithmetic used for the LoG sums (report.path). */
 enum { LOGFX_PATH_INT32 = 0, LOGFX_PATH_FP64 = 1 };
 
@@ -86,7 +90,8 @@ typedef struct {
  *   std_k      : >= 0.
  *   std5_max   : the paper's 5x5 first stage (Sec. 4.1).  Must be < 0 (off)
  *                in this build; >= 0 returns LOGFX_EUNSUPPORTED.
- *   smooth     : LOGFX_SMOOTH_NEVER or LOGFX_SMOOTH_ALWAYS (hybrid median).
+ *   smooth     : LOGFX_SMOOTH_NEVER, LOGFX_SMOOTH_ALWAYS (hybrid median) or
+ *                LOGFX_SMOOTH_GATE (the gate chooses per image).
  *   median_size: 3 or 5 (window of the hybrid median, Sec. 3.4).
  *   flags      : reserved, must be 0. */
 typedef struct {
@@ -111,6 +116,9 @@ typedef struct {
     int64_t output;       /* pixels set in the output (F, or E unsmoothed) */
     int32_t path;         /* LOGFX_PATH_INT32 or LOGFX_PATH_FP64           */
     int32_t smoothed;     /* 1 if the hybrid median was applied            */
+    int32_t gated;        /* 1 if the gate took the smoothing decision     */
+    int32_t gate_fallback;/* 1 if GATE was asked with no gate parameters   */
+    double gate_logit;    /* the gate's logit (gated calls), else 0        */
 } logfx_report;
 
 /* Library version string (static storage). */
@@ -217,6 +225,81 @@ int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_p
  * accumulation, as does enabling or disabling. */
 int logfx_timing_enable(logfx_ctx *ctx, int on);
 int logfx_timing_read(logfx_ctx *ctx, double *ms_out, int64_t *calls_out);
+
+/* ------------------------------------------------------------------------
+ * The smoothing gate.  The paper leaves the choice to smooth the extracted
+ * map or not to the user, according to its noise (abstract; Sec. 4).  The
+ * gate takes it per image from features that pass 1 gathers on the way:
+ *
+ *   features  3 x 128 x 128 per image.  The image is cut into 128 x 128
+ *             cells (row y and column x fall in cell (floor(128 y / H),
+ *             floor(128 x / W)); cells of images smaller than 128 in a
+ *             direction may be empty and give 0).  Per cell: the mean pixel
+ *             value / (2^bits - 1), and the fractions of pixels with a
+ *             non-zero crossing strength Z_1, Z_2 (Sec. 3.2).  Computed in
+ *             FP64 from exact integer sums, stored as bfloat16 (round to
+ *             nearest even), [n][3][128][128], channel order as listed.
+ *   network   conv 3x3, stride 2, zero padding 1, 3 -> 16 channels, ReLU;
+ *             conv 16 -> 32, ReLU; conv 32 -> 32, ReLU (128 -> 64 -> 32 ->
+ *             16); mean over the 16 x 16 positions; linear 32 -> 1 logit.
+ *             Smooth iff logit > 0.
+ *   numbers   bfloat16 features, convolution weights and stored
+ *             activations (and their masked gradients); FP32 accumulation
+ *             on the matrix cores; FP32 biases, head, loss and optimiser.
+ *   training  mean binary cross-entropy with logits; AdamW (beta1 0.9,
+ *             beta2 0.999, eps 1e-8, decoupled weight decay 1e-4 on every
+ *             parameter) on FP32 master parameters kept in the context.
+ *
+ * Parameters are a flat FP32 vector of LOGFX_GATE_NPARAM values:
+ *   w1[16][3][3][3] b1[16] w2[32][16][3][3] b2[32] w3[32][32][3][3] b3[32]
+ *   wf[32] bf[1]   (weights [out][in][ky][kx]; ky, kx = 0..2 for offsets
+ *   -1..1).
+ * Feature sets for the training calls are DEVICE arrays of bfloat16 bits
+ * [N][3][128][128]; idx (DEVICE int32 [B], nullable) selects the B samples
+ * of a batch (NULL: samples 0..B-1); labels are DEVICE floats [N] (0 or 1)
+ * indexed like the features.  All gate calls are asynchronous on `stream`
+ * except the parameter transfers, which complete before they return.
+ * ---------------------------------------------------------------------- */
+#define LOGFX_GATE_NPARAM 14369
+#define LOGFX_GATE_CELLS 128
+#define LOGFX_GATE_MAX_BATCH 4096
+
+/* Features of n images (pass 1 of the pipeline with the cell sums; the
+ * parameters are those of logfx_extract_batch, smooth is ignored).  Every
+ * cell must hold fewer than 2^32 pixels.  feats: DEVICE, n*3*128*128
+ * bfloat16 values. */
+int logfx_gate_features(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
+                        uint16_t *feats, void *stream);
+
+/* Set the gate's parameters from HOST memory (n must be LOGFX_GATE_NPARAM)
+ * and reset the optimiser state (moments and step count). */
+int logfx_gate_set_params(logfx_ctx *ctx, const float *theta, int64_t n);
+/* Copy the parameters to HOST memory (waits for the device). */
+int logfx_gate_get_params(logfx_ctx *ctx, float *theta, int64_t n);
+/* Parameters from / to a file: the 8 bytes "LOGFXGT1", int32 parameter
+ * count, int32 0, then the FP32 values, all little-endian. */
+int logfx_gate_load(logfx_ctx *ctx, const char *path);
+int logfx_gate_save(logfx_ctx *ctx, const char *path);
+
+/* Logits of B samples (1 <= B <= LOGFX_GATE_MAX_BATCH).  logits: DEVICE
+ * float[B]. */
+int logfx_gate_forward(logfx_ctx *ctx, int32_t B, const uint16_t *feats, const int32_t *idx,
+                       float *logits, void *stream);
+/* Gradient of the mean loss over B samples with respect to the parameters
+ * (forward and backward pass).  grad: DEVICE float[LOGFX_GATE_NPARAM] or
+ * NULL (then the context's gradient buffer, which logfx_gate_step uses);
+ * loss: DEVICE float[1] or NULL. */
+int logfx_gate_backward(logfx_ctx *ctx, int32_t B, const uint16_t *feats, const int32_t *idx,
+                        const float *labels, float *grad, float *loss, void *stream);
+/* One AdamW step with learning rate lr on a gradient (DEVICE, or NULL for
+ * the context's gradient buffer). */
+int logfx_gate_step(logfx_ctx *ctx, const float *grad, double lr, void *stream);
+
+/* The gate on n images: features, network, decision.  logits: DEVICE
+ * float[n] or NULL; decisions: DEVICE uint8[n] (1 = smooth) or NULL.
+ * Needs gate parameters (LOGFX_EINVAL otherwise). */
+int logfx_gate(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p, float *logits,
+               uint8_t *decisions, void *stream);
 
 #ifdef __cplusplus
 }

@@ -8,8 +8,8 @@
 namespace logfx {
 
 #define X(A, B)                                                                                   \
-    hipError_t pass1_i_r##A##_##B(const Pass1Args<OrbitTapsI> &, bool, int, hipStream_t, int *);  \
-    hipError_t pass1_d_r##A##_##B(const Pass1Args<OrbitTapsD> &, bool, int, hipStream_t, int *);  \
+    hipError_t pass1_i_r##A##_##B(const Pass1Args<OrbitTapsI> &, int, int, hipStream_t, int *);  \
+    hipError_t pass1_d_r##A##_##B(const Pass1Args<OrbitTapsD> &, int, int, hipStream_t, int *);  \
     hipError_t pass2_i_r##A##_##B(const Pass2Args<OrbitTapsI> &, int, hipStream_t, int *);        \
     hipError_t pass2_d_r##A##_##B(const Pass2Args<OrbitTapsD> &, int, hipStream_t, int *);
 LOGFX_RADII(X)
@@ -70,16 +70,16 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
 
 }  // namespace kern
 
-hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, int grid,
+hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, int mode, int grid,
                           hipStream_t s, int *max_grid) {
-#define X(A, B) if (ra == A && rb == B) return pass1_i_r##A##_##B(a, dbg, grid, s, max_grid);
+#define X(A, B) if (ra == A && rb == B) return pass1_i_r##A##_##B(a, mode, grid, s, max_grid);
     LOGFX_RADII(X)
 #undef X
     return hipErrorInvalidValue;
 }
-hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, int grid,
+hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, int mode, int grid,
                           hipStream_t s, int *max_grid) {
-#define X(A, B) if (ra == A && rb == B) return pass1_d_r##A##_##B(a, dbg, grid, s, max_grid);
+#define X(A, B) if (ra == A && rb == B) return pass1_d_r##A##_##B(a, mode, grid, s, max_grid);
     LOGFX_RADII(X)
 #undef X
     return hipErrorInvalidValue;

@@ -18,6 +18,7 @@
 #include <string>
 #include <vector>
 
+#include "logfx_gate.h"
 #include "logfx_internal.h"
 
 using namespace logfx;
@@ -83,6 +84,24 @@ struct logfx_ctx {
     std::vector<char> timed_graph;   // per timed call: 1 if it was a graph replay
     int alloc_count = 0;
     int fail_alloc_at = -1;          // test hook: LOGFX_FAIL_ALLOC=n fails the n-th allocation
+    // smoothing gate: parameters, optimiser state and workspaces
+    struct Gate {
+        float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;   // [kNParam]
+        uint16_t *wbf = nullptr;        // bfloat16 copy of theta
+        bool loaded = false;
+        long long step = 0;             // AdamW steps since the parameters were set
+        uint16_t *act = nullptr, *gact = nullptr;   // activations / gradients of a batch
+        float *small = nullptr;         // gap [B][32], logits [B], dz [B], loss [B]
+        float *partial = nullptr;       // split-K weight-gradient partials
+        long long capB = 0;
+        unsigned long long *cells = nullptr;   // [capImg][2][cells^2]
+        uint16_t *feats = nullptr;             // [capImg][3][cells^2]
+        int *flags = nullptr;                  // [capImg]
+        long long capImg = 0;
+        float *h_logits = nullptr;             // pinned report mirrors
+        int *h_flags = nullptr;
+        long long h_cap = 0, h_capf = 0;
+    } gate;
 };
 
 namespace {
@@ -183,6 +202,79 @@ int ensure_host(logfx_ctx *ctx, long long nimg, long long n2) {
     int rc;
     if ((rc = grow_host(ctx, ctx->h_stats, ctx->h_capn, nimg)) != LOGFX_OK) return rc;
     return grow_host(ctx, ctx->h_counts2, ctx->h_cap2, n2 * 2);
+}
+
+// Gate parameters, optimiser state and the bfloat16 copy (allocated once).
+int ensure_gate_params(logfx_ctx *ctx) {
+    auto &G = ctx->gate;
+    if (G.theta) return LOGFX_OK;
+    int rc;
+    if ((rc = realloc_dev(ctx, G.m, gate::kNParam)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.v, gate::kNParam)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.grad, gate::kNParam)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.wbf, gate::kNParam)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.theta, gate::kNParam)) != LOGFX_OK)
+        return rc;
+    return LOGFX_OK;
+}
+
+// Grow-only workspace of the network for batches of up to B samples.
+int ensure_gate_batch(logfx_ctx *ctx, long long B) {
+    auto &G = ctx->gate;
+    if (B <= G.capB) return LOGFX_OK;
+    G.capB = 0;
+    int rc;
+    if ((rc = realloc_dev(ctx, G.act, gate::act_elems((int)B))) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.gact, gate::act_elems((int)B))) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.small, B * (gate::kC3 + 3))) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.partial, gate::partial_elems((int)B))) != LOGFX_OK)
+        return rc;
+    G.capB = B;
+    return LOGFX_OK;
+}
+
+// Grow-only per-image gate scratch: cell sums, features, decisions.
+int ensure_gate_images(logfx_ctx *ctx, long long n) {
+    auto &G = ctx->gate;
+    if (n <= G.capImg) return LOGFX_OK;
+    G.capImg = 0;
+    int rc;
+    if ((rc = realloc_dev(ctx, G.cells, n * 2 * gate::kCellCount)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.feats, n * gate::kFeatC * gate::kCellCount)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.flags, n)) != LOGFX_OK)
+        return rc;
+    G.capImg = n;
+    return LOGFX_OK;
+}
+
+// The network's buffers for a batch of B <= capB samples.
+gate::NetBuffers net_buffers(logfx_ctx *ctx, int B, const uint16_t *feats, const int *idx, const float *labels,
+                             float *grad, float *loss) {
+    using namespace gate;
+    auto &G = ctx->gate;
+    NetBuffers n;
+    std::memset(&n, 0, sizeof n);
+    const long long e1 = (long long)B * kC1 * kH1 * kH1, e2 = (long long)B * kC2 * kH2 * kH2;
+    n.x0 = feats;
+    n.idx = idx;
+    n.w = G.wbf;
+    n.theta = G.theta;
+    n.a1 = G.act;
+    n.a2 = G.act + e1;
+    n.a3 = G.act + e1 + e2;
+    n.g1 = G.gact;
+    n.g2 = G.gact + e1;
+    n.g3 = G.gact + e1 + e2;
+    n.gap = G.small;
+    n.logits = G.small + (long long)B * kC3;
+    n.dz = n.logits + B;
+    n.lossb = n.dz + B;
+    n.labels = labels;
+    n.grad = grad ? grad : G.grad;
+    n.loss = loss;
+    n.partial = G.partial;
+    n.B = B;
+    return n;
 }
 
 // Events of timed call number `call` (created on first use).
@@ -289,7 +381,7 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     if (p->std5_max >= 0.0)
         return set_err(ctx, LOGFX_EUNSUPPORTED, "the 5x5 first deviation stage (std5_max >= 0) "
                                                 "is not supported in this build");
-    if (p->smooth != LOGFX_SMOOTH_NEVER && p->smooth != LOGFX_SMOOTH_ALWAYS)
+    if (p->smooth != LOGFX_SMOOTH_NEVER && p->smooth != LOGFX_SMOOTH_ALWAYS && p->smooth != LOGFX_SMOOTH_GATE)
         return set_err(ctx, LOGFX_EINVAL, "unknown smooth mode %d", p->smooth);
     if (p->median_size != 3 && p->median_size != 5)
         return set_err(ctx, LOGFX_EINVAL, "median_size %d is not 3 or 5", p->median_size);
@@ -476,7 +568,19 @@ struct Launches {
     int grid1, grid2;
     int path, ra, rb;
     bool dbg;
+    // smoothing gate
+    bool features;                 // pass 1 sums the cells; the features are finished after it
+    bool gated;                    // the network decides the median per image before pass 2
+    unsigned long long *cells;
+    uint16_t *feats;
+    double maxval;
+    gate::NetBuffers net;
+    int *flags;
+    uint8_t *decisions;            // optional copy of the decisions (logfx_gate)
 };
+
+// How far a call runs.
+enum Until { UNTIL_PASS1 = 0, UNTIL_FEATURES = 1, UNTIL_DECISION = 2, UNTIL_OUTPUT = 3 };
 
 template <class Taps, class V>
 void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *const L[2],
@@ -502,31 +606,79 @@ void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *con
     a2.rows = ctx->tiles.rows2;
     a2.stats = ctx->stats;
     a2.counts = ctx->counts2;
-    a2.smooth = p->smooth == LOGFX_SMOOTH_ALWAYS;
+    a2.smooth = p->smooth != LOGFX_SMOOTH_NEVER;   // GATE without a gate falls back to ALWAYS
     a2.median_size = p->median_size;
 }
 
-hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, bool maps_only) {
+hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int until) {
     hipError_t e;
     const bool i32 = k.path == LOGFX_PATH_INT32;
-    e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, k.dbg, k.grid1, s)
-            : launch_pass1_d(k.ra, k.rb, k.p1.d, k.dbg, k.grid1, s);
-    if (e != hipSuccess || maps_only) return e;
+    const int mode = k.dbg ? 1 : k.features ? 2 : 0;
+    if (k.features && (e = gate::launch_zero_cells(k.cells, k.fin.L.nimg, s)) != hipSuccess) return e;
+    e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, mode, k.grid1, s)
+            : launch_pass1_d(k.ra, k.rb, k.p1.d, mode, k.grid1, s);
+    if (e != hipSuccess || until == UNTIL_PASS1) return e;
+    if (until < UNTIL_OUTPUT) {   // the gate alone: no thresholds needed
+        if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, s)) != hipSuccess) return e;
+        if (until == UNTIL_FEATURES) return hipSuccess;
+        if ((e = gate::launch_forward(k.net, s)) != hipSuccess) return e;
+        return gate::launch_decide(k.net.logits, k.flags, k.decisions, k.fin.L.nimg, s);
+    }
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if ((e = launch_finalize(k.fin, s)) != hipSuccess) return e;
+    if (k.gated) {
+        if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, s)) != hipSuccess ||
+            (e = gate::launch_forward(k.net, s)) != hipSuccess ||
+            (e = gate::launch_decide(k.net.logits, k.flags, k.decisions, k.fin.L.nimg, s)) != hipSuccess)
+            return e;
+    }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     return i32 ? launch_pass2_i(k.ra, k.rb, k.p2.i, k.grid2, s)
                : launch_pass2_d(k.ra, k.rb, k.p2.d, k.grid2, s);
 }
 
+// Every cell of the gate's feature grid must hold fewer than 2^32 pixels.
+int check_cells(logfx_ctx *ctx, int n, const logfx_image *imgs) {
+    for (int i = 0; i < n; ++i) {
+        const long long ch = (imgs[i].height + gate::kCells - 1) / gate::kCells;
+        const long long cw = (imgs[i].width + gate::kCells - 1) / gate::kCells;
+        if (ch * cw >= (1LL << 32))
+            return set_err(ctx, LOGFX_EUNSUPPORTED, "image %d: gate cells of more than 2^32 pixels", i);
+    }
+    if (n > LOGFX_GATE_MAX_BATCH)
+        return set_err(ctx, LOGFX_EUNSUPPORTED, "the gate takes at most %d images per call", LOGFX_GATE_MAX_BATCH);
+    return LOGFX_OK;
+}
+
+// gate: 0 none, 1 features only (into feats), 2 features + network
+// (decisions in the context's flags).
 int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double *const L[2],
-                   double *const Z[2], Launches &k) {
+                   double *const Z[2], Launches &k, int gate = 0, uint16_t *feats = nullptr) {
     std::memset(&k, 0, sizeof k);
     k.path = c.pl.path;
     k.ra = c.pl.ra;
     k.rb = c.pl.rb;
     if (k.path == LOGFX_PATH_INT32) fill_args<OrbitTapsI, int>(c, ctx, p, L, Z, k.p1.i, k.p2.i, k.dbg);
     else fill_args<OrbitTapsD, double>(c, ctx, p, L, Z, k.p1.d, k.p2.d, k.dbg);
+    if (gate > 0) {
+        auto &G = ctx->gate;
+        int rc;
+        if ((rc = ensure_gate_images(ctx, c.n)) != LOGFX_OK) return rc;
+        k.features = true;
+        k.cells = G.cells;
+        k.feats = feats ? feats : G.feats;
+        k.maxval = c.pl.maxpix;
+        if (k.path == LOGFX_PATH_INT32) k.p1.i.cells = G.cells;
+        else k.p1.d.cells = G.cells;
+        if (gate > 1) {
+            if ((rc = ensure_gate_batch(ctx, c.n)) != LOGFX_OK) return rc;
+            k.gated = true;
+            k.net = net_buffers(ctx, c.n, k.feats, nullptr, nullptr, nullptr, nullptr);
+            k.flags = G.flags;
+            if (k.path == LOGFX_PATH_INT32) k.p2.i.med_flags = G.flags;
+            else k.p2.d.med_flags = G.flags;
+        }
+    }
     k.fin.L = c.L;
     k.fin.partials = ctx->partials;
     k.fin.counts = ctx->counts1;
@@ -567,7 +719,7 @@ int graph_launch(logfx_ctx *ctx, const Launches &k, hipStream_t s) {
             return hip_err(ctx, e, "hipStreamCreate");
         if ((e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_err(ctx, e, "hipStreamBeginCapture");
-        hipError_t le = launch_all(k, ctx->capture, nullptr, false);
+        hipError_t le = launch_all(k, ctx->capture, nullptr, UNTIL_OUTPUT);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(ctx->capture, &g);
         if (le != hipSuccess) {
@@ -588,11 +740,21 @@ int graph_launch(logfx_ctx *ctx, const Launches &k, hipStream_t s) {
     return LOGFX_OK;
 }
 
-int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, logfx_report *reps,
+int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, const Launches &k, logfx_report *reps,
                  hipStream_t s) {
     int rc;
     if ((rc = ensure_host(ctx, c.n, c.L.total2)) != LOGFX_OK) return rc;
+    auto &G = ctx->gate;
     hipError_t e;
+    if (k.gated) {
+        if ((rc = grow_host(ctx, G.h_logits, G.h_cap, c.n)) != LOGFX_OK ||
+            (rc = grow_host(ctx, G.h_flags, G.h_capf, c.n)) != LOGFX_OK)
+            return rc;
+        if ((e = hipMemcpyAsync(G.h_logits, k.net.logits, sizeof(float) * c.n, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(G.h_flags, k.flags, sizeof(int) * c.n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_err(ctx, e, "report copy");
+    }
     if ((e = hipMemcpyAsync(ctx->h_stats, ctx->stats, sizeof(DevStats) * c.n, hipMemcpyDeviceToHost, s)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(ctx->h_counts2, ctx->counts2, sizeof(int) * 2 * (size_t)c.L.total2,
@@ -618,7 +780,14 @@ int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, logfx_rep
         }
         b2 += c.tiles[i].ntiles2;
         r.path = c.pl.path;
-        r.smoothed = p->smooth == LOGFX_SMOOTH_ALWAYS;
+        r.smoothed = p->smooth != LOGFX_SMOOTH_NEVER;
+        if (k.gated) {
+            r.gated = 1;
+            r.smoothed = G.h_flags[i] != 0;
+            r.gate_logit = G.h_logits[i];
+        } else if (p->smooth == LOGFX_SMOOTH_GATE) {
+            r.gate_fallback = 1;
+        }
     }
     return LOGFX_OK;
 }
@@ -634,8 +803,10 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
     Call c;
     int rc = prepare(ctx, n, imgs, p, outs, !maps, c, s);
     if (rc != LOGFX_OK) return rc;
+    const bool gated = !maps && p->smooth == LOGFX_SMOOTH_GATE && ctx->gate.loaded;
+    if (gated && (rc = check_cells(ctx, n, imgs)) != LOGFX_OK) return rc;
     Launches k;
-    if ((rc = build_launches(ctx, c, p, maps_L, maps_Z, k)) != LOGFX_OK) return rc;
+    if ((rc = build_launches(ctx, c, p, maps_L, maps_Z, k, gated ? 2 : 0)) != LOGFX_OK) return rc;
     hipError_t e;
     const bool use_graph = n > 1 && ctx->graph && !maps;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -646,7 +817,7 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
     }
     if (use_graph) {
         if ((rc = graph_launch(ctx, k, s)) != LOGFX_OK) return rc;
-    } else if ((e = launch_all(k, s, timed ? ev : nullptr, maps)) != hipSuccess) {
+    } else if ((e = launch_all(k, s, timed ? ev : nullptr, maps ? UNTIL_PASS1 : UNTIL_OUTPUT)) != hipSuccess) {
         return hip_err(ctx, e, "kernel launch");
     }
     if (maps) return LOGFX_OK;
@@ -656,7 +827,46 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
         ctx->timed_graph[ctx->timed_calls] = use_graph;
         ++ctx->timed_calls;
     }
-    if (reps) return fill_reports(ctx, c, p, reps, s);
+    if (reps) return fill_reports(ctx, c, p, k, reps, s);
+    return LOGFX_OK;
+}
+
+// Features, or features and decisions, of n images (no pass 2).
+int run_gate(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, uint16_t *feats,
+             float *logits, uint8_t *decisions, int until, void *stream) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
+    if (until == UNTIL_DECISION && !ctx->gate.loaded)
+        return set_err(ctx, LOGFX_EINVAL, "the gate has no parameters (logfx_gate_set_params / logfx_gate_load)");
+    if (until == UNTIL_FEATURES && !feats) return set_err(ctx, LOGFX_EINVAL, "feats is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    Call c;
+    int rc = prepare(ctx, n, imgs, p, nullptr, false, c, s);
+    if (rc != LOGFX_OK) return rc;
+    if ((rc = check_cells(ctx, n, imgs)) != LOGFX_OK) return rc;
+    Launches k;
+    if ((rc = build_launches(ctx, c, p, nullptr, nullptr, k, until == UNTIL_FEATURES ? 1 : 2, feats)) != LOGFX_OK)
+        return rc;
+    k.decisions = decisions;
+    hipError_t e;
+    if ((e = launch_all(k, s, nullptr, until)) != hipSuccess) return hip_err(ctx, e, "kernel launch");
+    if (logits && (e = hipMemcpyAsync(logits, k.net.logits, sizeof(float) * n, hipMemcpyDeviceToDevice, s)) !=
+                      hipSuccess)
+        return hip_err(ctx, e, "logit copy");
+    return LOGFX_OK;
+}
+
+// Checks shared by the network calls.
+int gate_batch_args(logfx_ctx *ctx, int B, const uint16_t *feats) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (B < 1 || B > LOGFX_GATE_MAX_BATCH)
+        return set_err(ctx, LOGFX_EINVAL, "batch %d not in 1..%d", B, LOGFX_GATE_MAX_BATCH);
+    if (!feats) return set_err(ctx, LOGFX_EINVAL, "feats is NULL");
+    if (!ctx->gate.loaded)
+        return set_err(ctx, LOGFX_EINVAL, "the gate has no parameters (logfx_gate_set_params / logfx_gate_load)");
     return LOGFX_OK;
 }
 
@@ -675,7 +885,8 @@ std::string tune_key(logfx_ctx *ctx, const Call &c, const logfx_params *p, const
     std::ostringstream k;
     k << arch << "|" << (c.pl.path == LOGFX_PATH_INT32 ? "int32" : "fp64") << "|r" << c.pl.ra << c.pl.rb
       << "|" << (img0->dtype == LOGFX_U8 ? "u8" : "u16") << "|med"
-      << (p->smooth == LOGFX_SMOOTH_ALWAYS ? p->median_size : 0) << "|" << (c.n > 1 ? "batch" : "single");
+      << (p->smooth != LOGFX_SMOOTH_NEVER ? p->median_size : 0) << (p->smooth == LOGFX_SMOOTH_GATE ? "g" : "")
+      << "|" << (c.n > 1 ? "batch" : "single");
     return k.str();
 }
 
@@ -763,6 +974,13 @@ int logfx_destroy(logfx_ctx *ctx) {
         if (ctx->h_owner1) (void)hipHostFree(ctx->h_owner1);
         if (ctx->h_owner2) (void)hipHostFree(ctx->h_owner2);
         for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
+        auto &G = ctx->gate;
+        for (void *q : {(void *)G.theta, (void *)G.m, (void *)G.v, (void *)G.grad, (void *)G.wbf, (void *)G.act,
+                        (void *)G.gact, (void *)G.small, (void *)G.partial, (void *)G.cells, (void *)G.feats,
+                        (void *)G.flags})
+            (void)hipFree(q);
+        if (G.h_logits) (void)hipHostFree(G.h_logits);
+        if (G.h_flags) (void)hipHostFree(G.h_flags);
     }
     delete ctx;
     return LOGFX_OK;
@@ -889,6 +1107,145 @@ int logfx_timing_read(logfx_ctx *ctx, double *ms_out, int64_t *calls_out) {
     }
     if (calls_out) *calls_out = ctx->timed_calls;
     ctx->timed_calls = 0;
+    return LOGFX_OK;
+}
+
+int logfx_gate_features(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
+                        uint16_t *feats, void *stream) {
+    return run_gate(ctx, n, imgs, p, feats, nullptr, nullptr, UNTIL_FEATURES, stream);
+}
+
+int logfx_gate(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p, float *logits,
+               uint8_t *decisions, void *stream) {
+    return run_gate(ctx, n, imgs, p, nullptr, logits, decisions, UNTIL_DECISION, stream);
+}
+
+int logfx_gate_set_params(logfx_ctx *ctx, const float *theta, int64_t n) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!theta) return set_err(ctx, LOGFX_EINVAL, "theta is NULL");
+    if (n != gate::kNParam) return set_err(ctx, LOGFX_EINVAL, "%lld parameters, the gate has %d", (long long)n, gate::kNParam);
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(theta[i])) return set_err(ctx, LOGFX_EINVAL, "parameter %lld is not finite", (long long)i);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
+    int rc;
+    if ((rc = ensure_gate_params(ctx)) != LOGFX_OK) return rc;
+    auto &G = ctx->gate;
+    const size_t bytes = sizeof(float) * gate::kNParam;
+    hipError_t e;
+    if ((e = hipMemcpy(G.theta, theta, bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(G.m, 0, bytes)) != hipSuccess || (e = hipMemset(G.v, 0, bytes)) != hipSuccess ||
+        (e = gate::launch_to_bf16(G.theta, G.wbf, gate::kNParam, nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess)
+        return hip_err(ctx, e, "gate parameters");
+    G.step = 0;
+    G.loaded = true;
+    return LOGFX_OK;
+}
+
+int logfx_gate_get_params(logfx_ctx *ctx, float *theta, int64_t n) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!theta) return set_err(ctx, LOGFX_EINVAL, "theta is NULL");
+    if (n != gate::kNParam) return set_err(ctx, LOGFX_EINVAL, "%lld parameters, the gate has %d", (long long)n, gate::kNParam);
+    if (!ctx->gate.loaded) return set_err(ctx, LOGFX_EINVAL, "the gate has no parameters");
+    DeviceGuard dg(ctx->device);
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(theta, ctx->gate.theta, sizeof(float) * gate::kNParam, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_err(ctx, e, "gate parameters");
+    return LOGFX_OK;
+}
+
+int logfx_gate_load(logfx_ctx *ctx, const char *path) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    if (!path) return set_err(ctx, LOGFX_EINVAL, "path is NULL");
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return set_err(ctx, LOGFX_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[2];
+    std::vector<float> theta(gate::kNParam);
+    f.read(magic, 8);
+    f.read(reinterpret_cast<char *>(hdr), sizeof hdr);
+    if (!f || std::memcmp(magic, "LOGFXGT1", 8) != 0 || hdr[0] != gate::kNParam || hdr[1] != 0)
+        return set_err(ctx, LOGFX_EINVAL, "%s is not a gate parameter file of %d values", path, gate::kNParam);
+    f.read(reinterpret_cast<char *>(theta.data()), sizeof(float) * gate::kNParam);
+    if (!f) return set_err(ctx, LOGFX_EINVAL, "%s is truncated", path);
+    return logfx_gate_set_params(ctx, theta.data(), gate::kNParam);
+}
+
+int logfx_gate_save(logfx_ctx *ctx, const char *path) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    if (!path) return set_err(ctx, LOGFX_EINVAL, "path is NULL");
+    std::vector<float> theta(gate::kNParam);
+    int rc = logfx_gate_get_params(ctx, theta.data(), gate::kNParam);
+    if (rc != LOGFX_OK) return rc;
+    std::ofstream f(path, std::ios::binary | std::ios::trunc);
+    const int32_t hdr[2] = {gate::kNParam, 0};
+    f.write("LOGFXGT1", 8);
+    f.write(reinterpret_cast<const char *>(hdr), sizeof hdr);
+    f.write(reinterpret_cast<const char *>(theta.data()), sizeof(float) * gate::kNParam);
+    if (!f) return set_err(ctx, LOGFX_EINVAL, "cannot write %s", path);
+    return LOGFX_OK;
+}
+
+int logfx_gate_forward(logfx_ctx *ctx, int32_t B, const uint16_t *feats, const int32_t *idx, float *logits,
+                       void *stream) {
+    int rc = gate_batch_args(ctx, B, feats);
+    if (rc != LOGFX_OK) return rc;
+    if (!logits) return set_err(ctx, LOGFX_EINVAL, "logits is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = ensure_gate_batch(ctx, B)) != LOGFX_OK) return rc;
+    const gate::NetBuffers n = net_buffers(ctx, B, feats, idx, nullptr, nullptr, nullptr);
+    hipError_t e;
+    if ((e = gate::launch_forward(n, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(logits, n.logits, sizeof(float) * B, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_err(ctx, e, "gate forward");
+    return LOGFX_OK;
+}
+
+int logfx_gate_backward(logfx_ctx *ctx, int32_t B, const uint16_t *feats, const int32_t *idx, const float *labels,
+                        float *grad, float *loss, void *stream) {
+    int rc = gate_batch_args(ctx, B, feats);
+    if (rc != LOGFX_OK) return rc;
+    if (!labels) return set_err(ctx, LOGFX_EINVAL, "labels is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = ensure_gate_batch(ctx, B)) != LOGFX_OK) return rc;
+    const gate::NetBuffers n = net_buffers(ctx, B, feats, idx, labels, grad, loss);
+    hipError_t e;
+    if ((e = gate::launch_forward(n, s)) != hipSuccess || (e = gate::launch_backward(n, s)) != hipSuccess)
+        return hip_err(ctx, e, "gate backward");
+    return LOGFX_OK;
+}
+
+int logfx_gate_step(logfx_ctx *ctx, const float *grad, double lr, void *stream) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!ctx->gate.loaded) return set_err(ctx, LOGFX_EINVAL, "the gate has no parameters");
+    if (!(lr >= 0.0) || !std::isfinite(lr)) return set_err(ctx, LOGFX_EINVAL, "lr must be finite and >= 0");
+    DeviceGuard dg(ctx->device);
+    auto &G = ctx->gate;
+    const long long t = ++G.step;
+    gate::AdamArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.theta = G.theta;
+    a.m = G.m;
+    a.v = G.v;
+    a.grad = grad ? grad : G.grad;
+    a.wbf = G.wbf;
+    a.lr = (float)lr;
+    a.beta1 = 0.9f;
+    a.beta2 = 0.999f;
+    a.eps = 1e-8f;
+    a.wd = 1e-4f;
+    a.bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+    a.bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+    a.n = gate::kNParam;
+    hipError_t e = gate::launch_adamw(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_err(ctx, e, "gate step");
     return LOGFX_OK;
 }
 

@@ -18,6 +18,10 @@ constexpr int kMaxOrbits = (kMaxRadius + 1) * (kMaxRadius + 2) / 2;
 constexpr int kHalo1 = 1;
 constexpr int kHalo2 = 4;
 
+// Side of the cell grid over which pass 1 sums the smoothing gate's
+// features (kGateCells x kGateCells cells per image).
+constexpr int kGateCells = 128;
+
 // Orbit index of the D4 orbit {(+-i, +-j), (+-j, +-i)}, 0 <= j <= i.
 __host__ __device__ constexpr int orbit_index(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -88,6 +92,10 @@ struct Pass1Args {
     double *dbgL[2];
     double *dbgZ[2];
     double unit[2];
+    // Gate features (mode 2): [nimg][2][kGateCells^2] counters, zeroed
+    // before the launch; plane 0 sums pixel values, plane 1 sums
+    // [Z_1 != 0] + 2^32 [Z_2 != 0] (every cell must hold < 2^32 pixels).
+    unsigned long long *cells;
 };
 
 template <class Taps>
@@ -101,6 +109,7 @@ struct Pass2Args {
     int *counts;            // [total2][2]: E pixels, output pixels per tile
     int smooth;             // 0 = E, 1 = hybrid median of E
     int median_size;        // 3 or 5
+    const int *med_flags;   // [nimg] or nullptr: when given, image i is smoothed iff med_flags[i] != 0
 };
 
 struct FinalizeArgs {
@@ -113,14 +122,16 @@ struct FinalizeArgs {
     DevStats *stats;       // [nimg]
 };
 
-// Launchers (defined in logfx_kernels.hip).  They return hipSuccess or the
+// Launchers (defined in logfx_dispatch.hip).  They return hipSuccess or the
 // launch error.  ra <= rb are the radii of the two masks.  grid = number of
 // workgroups (at most the number of tiles; fewer makes the launch
 // persistent).  max_grid, when non-null, receives the number of workgroups
 // that fit on the device at once and nothing is launched.
-hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, bool dbg, int grid,
+// mode: 0 statistics only, 1 also the FP64 maps (dbgL / dbgZ), 2 also the
+// gate's cell sums (cells); modes 1 and 2 run one tile per workgroup.
+hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, int mode, int grid,
                           hipStream_t s, int *max_grid = nullptr);
-hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, bool dbg, int grid,
+hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, int mode, int grid,
                           hipStream_t s, int *max_grid = nullptr);
 hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s,
                           int *max_grid = nullptr);

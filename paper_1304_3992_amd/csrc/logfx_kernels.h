@@ -320,6 +320,7 @@ __device__ inline void ring_push(T (&ring)[N], T v, int row, int H) {
 }
 
 template <bool B> using bool_c = std::integral_constant<bool, B>;
+template <int V> using int_c = std::integral_constant<int, V>;
 
 // ------------------------------------------------------------- work list
 // Tiles of a launch are split into 8 contiguous shares, one per XCD
@@ -353,7 +354,9 @@ __device__ inline ImageJob job_of(const Launch &L, int image) {
 // FP64 path keeps its registers.
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
 
-template <class Acc, int RA, int RB, bool DBG, bool LOOP>
+// MODE: 0 = statistics only; 1 = also the FP64 maps of a single image;
+// 2 = also the per-cell sums of the gate features.
+template <class Acc, int RA, int RB, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ double red[4][8];
@@ -375,6 +378,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
     const int nsteps = g.Rv + 2 * HL;
     const int t0 = g.y0 - HL;
     const uint16_t *lrow = lds + (2 * RB) * g.stride + g.lc;   // LDS row of step si
+
+    // Feature mode: the image is cut into kGateCells x kGateCells cells
+    // (row r and column x belong to cell (r * cells / H, x * cells / W)).
+    // Each lane sums its pixel values and crossing indicators down its
+    // column while the rows stay in one cell row; at the end of a cell row
+    // (or of the strip) the lanes of each cell are summed across the wave
+    // and one lane per cell adds the sums to the image's cell counters.
+    unsigned fv = 0, fc = 0;    // value sum; crossings of mask 1 + 2^16 * of mask 2
+    int fkey = 0, fcy = 0;      // this lane's cell column; current cell row
+    long long fnext = 0;        // first row of the next cell row
+    unsigned long long *fcells = nullptr;
+    if constexpr (MODE == 2) {
+        fkey = g.outc ? (int)(((long long)g.xc * kGateCells) / g.W) : (g.lane < HL ? -1 : kGateCells);
+        fcy = (int)(((long long)g.y0 * kGateCells) / g.H);
+        fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) / kGateCells;
+        fcells = a.cells + (long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) * 2 * kGateCells * kGateCells;
+    }
+    auto flush = [&](const int r) __attribute__((always_inline)) {
+        unsigned v = fv, c = fc;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {   // segmented inclusive scan over equal keys
+            const unsigned v2 = __shfl_up(v, off), c2 = __shfl_up(c, off);
+            const int k2 = __shfl_up(fkey, off);
+            if (g.lane >= off && k2 == fkey) v += v2, c += c2;
+        }
+        const int kn = __shfl_down(fkey, 1);
+        if (g.outc && (g.lane == kWave - 1 || kn != fkey) && (v | c)) {
+            unsigned long long *cell = fcells + (long long)fcy * kGateCells + fkey;
+            atomicAdd(cell, (unsigned long long)v);
+            atomicAdd(cell + kGateCells * kGateCells,
+                      (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
+        }
+        fv = fc = 0;
+        fcy = (int)(((long long)(r + 1) * kGateCells) / g.H);
+        fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) / kGateCells;
+    };
 
     // One step = one new input row.  Full groups of P steps are unrolled so
     // the register rings rotate by renaming; the last partial group runs
@@ -405,13 +444,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
             sz[j] += zu;
             sq[j] = __fma_rn(zu, zu, sq[j]);
             cnt[j] += __popcll(__ballot(zu != 0.0));   // wave-uniform
-            if constexpr (DBG) {
+            if constexpr (MODE == 2) fc += (unsigned)(zu != 0.0) << (16 * j);
+            if constexpr (MODE == 1) {
                 if (use) {
                     const long long at = (long long)r * g.W + g.xc;
                     if (a.dbgL[j]) a.dbgL[j][at] = AccOps<Acc>::to_d(c) * a.unit[j];
                     if (a.dbgZ[j]) a.dbgZ[j][at] = z * a.unit[j];
                 }
             }
+        }
+        if constexpr (MODE == 2) {
+            fv += use ? (unsigned)h[RB - 1][0] : 0u;   // pixel (r, xc)
+            if (si >= 2 && (r + 1 == fnext || r == g.y0 + g.Rv - 1)) flush(r);
         }
     };
     auto run = [&](auto clamp) __attribute__((always_inline)) {
@@ -459,14 +503,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
 }
 
 // ------------------------------------------------------------- pass 2
-// MED: 0 = no smoothing (output E), 3 or 5 = hybrid median window.
+// MED: 0 = no smoothing (output E), 3 or 5 = hybrid median window, -3 or
+// -5 = that window on the images whose med_flags entry is set, none on the
+// others (one kernel; the choice is uniform over a workgroup).
 template <class Acc, int RA, int RB, int MED, bool LOOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ int redc[2][8];
     constexpr int HL = kHalo2, P = 2 * RB + 1;
 
-    for_each_tile<LOOP>(a.L.total2, [&](const int item) __attribute__((always_inline)) {
+    auto tile = [&](const int item, auto medc) __attribute__((always_inline)) {
+    constexpr int M = decltype(medc)::value;
     const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
     const ImageJob J = job_of(a.L, image);
     const Strip<HL, RB> g(J.img, item - J.base2, J.tiles_x2, a.rows);
@@ -539,8 +586,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
         ring_push<C>(e, clamp_bits(__ballot(ej), lo_lane, hi_lane), t - 2, g.H);
         // output row t - 4 (from the ninth step on)
         uint64_t f;
-        if constexpr (MED == 0) f = e[2];
-        else if constexpr (MED == 3) f = hmed3(e);
+        if constexpr (M == 0) f = e[2];
+        else if constexpr (M == 3) f = hmed3(e);
         else f = hmed5(e);
         if (si >= 8) {
             if (g.outc) *orow = (uint8_t)((f & mybit) != 0);
@@ -579,6 +626,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
         a.counts[(long long)item * 2 + 1] = s1;
     }
     __syncthreads();   // LDS and the reduction buffers are reused by the next tile
+    };
+    for_each_tile<LOOP>(a.L.total2, [&](const int item) __attribute__((always_inline)) {
+        if constexpr (MED >= 0) {
+            tile(item, int_c<MED>{});
+        } else {   // gated: the median of each image as its flag says
+            const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
+            if (a.med_flags[image]) tile(item, int_c<-MED>{});
+            else tile(item, int_c<0>{});
+        }
     });
 }
 
@@ -594,23 +650,22 @@ hipError_t occupancy(K k, size_t shm, int *max_grid) {
     return e;
 }
 
-template <class Acc, int RA, int RB, bool DBG>
+template <class Acc, int RA, int RB, int MODE>
 hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
     const size_t shm = lds_bytes(a.rows, kHalo1, RB);
-    // the map-writing variant is for single images only: always one tile
-    // per workgroup
-    if constexpr (DBG) {
-        if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, DBG, false>, shm, max_grid);
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG, false>), dim3(a.L.total1),
+    // the map-writing and feature variants always run one tile per workgroup
+    if constexpr (MODE != 0) {
+        if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, false>, shm, max_grid);
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, false>), dim3(a.L.total1),
                            dim3(kTileWaves * kWave), shm, s, a);
         return hipGetLastError();
     }
-    if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, DBG, true>, shm, max_grid);
+    if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, 0, true>, shm, max_grid);
     if (grid >= a.L.total1)
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG, false>), dim3(a.L.total1),
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, 0, false>), dim3(a.L.total1),
                            dim3(kTileWaves * kWave), shm, s, a);
     else
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, DBG, true>), dim3(grid),
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, 0, true>), dim3(grid),
                            dim3(kTileWaves * kWave), shm, s, a);
     return hipGetLastError();
 }
@@ -618,6 +673,12 @@ hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStrea
 template <class Acc, int RA, int RB, int MED>
 hipError_t p2m(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
     const size_t shm = lds_bytes(a.rows, kHalo2, RB);
+    if constexpr (MED < 0) {   // gated variants run one tile per workgroup
+        if (max_grid) return occupancy(pass2_kernel<Acc, RA, RB, MED, false>, shm, max_grid);
+        hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, false>), dim3(a.L.total2),
+                           dim3(kTileWaves * kWave), shm, s, a);
+        return hipGetLastError();
+    }
     if (max_grid) return occupancy(pass2_kernel<Acc, RA, RB, MED, true>, shm, max_grid);
     if (grid >= a.L.total2)
         hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, false>), dim3(a.L.total2),
@@ -629,6 +690,11 @@ hipError_t p2m(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStre
 }
 template <class Acc, int RA, int RB>
 hipError_t p2(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
+    if (a.med_flags) {   // gated: one workgroup per tile
+        const int g = max_grid ? 0 : a.L.total2;
+        if (a.median_size == 3) return p2m<Acc, RA, RB, -3>(a, g, s, max_grid);
+        return p2m<Acc, RA, RB, -5>(a, g, s, max_grid);
+    }
     if (!a.smooth) return p2m<Acc, RA, RB, 0>(a, grid, s, max_grid);
     if (a.median_size == 3) return p2m<Acc, RA, RB, 3>(a, grid, s, max_grid);
     return p2m<Acc, RA, RB, 5>(a, grid, s, max_grid);

@@ -14,15 +14,17 @@
 
 namespace logfx {
 
-hipError_t LOGFX_FN(pass1_i)(const Pass1Args<OrbitTapsI> &a, bool dbg, int grid, hipStream_t s,
+hipError_t LOGFX_FN(pass1_i)(const Pass1Args<OrbitTapsI> &a, int mode, int grid, hipStream_t s,
                              int *max_grid) {
-    return dbg ? kern::p1<int, LOGFX_RA, LOGFX_RB, true>(a, grid, s, max_grid)
-               : kern::p1<int, LOGFX_RA, LOGFX_RB, false>(a, grid, s, max_grid);
+    if (mode == 1) return kern::p1<int, LOGFX_RA, LOGFX_RB, 1>(a, grid, s, max_grid);
+    if (mode == 2) return kern::p1<int, LOGFX_RA, LOGFX_RB, 2>(a, grid, s, max_grid);
+    return kern::p1<int, LOGFX_RA, LOGFX_RB, 0>(a, grid, s, max_grid);
 }
-hipError_t LOGFX_FN(pass1_d)(const Pass1Args<OrbitTapsD> &a, bool dbg, int grid, hipStream_t s,
+hipError_t LOGFX_FN(pass1_d)(const Pass1Args<OrbitTapsD> &a, int mode, int grid, hipStream_t s,
                              int *max_grid) {
-    return dbg ? kern::p1<double, LOGFX_RA, LOGFX_RB, true>(a, grid, s, max_grid)
-               : kern::p1<double, LOGFX_RA, LOGFX_RB, false>(a, grid, s, max_grid);
+    if (mode == 1) return kern::p1<double, LOGFX_RA, LOGFX_RB, 1>(a, grid, s, max_grid);
+    if (mode == 2) return kern::p1<double, LOGFX_RA, LOGFX_RB, 2>(a, grid, s, max_grid);
+    return kern::p1<double, LOGFX_RA, LOGFX_RB, 0>(a, grid, s, max_grid);
 }
 hipError_t LOGFX_FN(pass2_i)(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s, int *max_grid) {
     return kern::p2<int, LOGFX_RA, LOGFX_RB>(a, grid, s, max_grid);

@@ -18,13 +18,17 @@ LIB_PATH = os.path.join(_HERE, "liblogfx.so")
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE = 0, 1, 2, 3, 4
 U8, U16 = 0, 1
 STD_REL, STD_ABS = 0, 1
-SMOOTH_NEVER, SMOOTH_ALWAYS = 0, 1
+SMOOTH_NEVER, SMOOTH_ALWAYS, SMOOTH_GATE = 0, 1, 2
 PATH_INT32, PATH_FP64 = 0, 1
 
 EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_make_log_mask", "logfx_check_params", "logfx_extract", "logfx_extract_maps",
            "logfx_timing_enable", "logfx_timing_read", "logfx_extract_batch",
-           "logfx_set_option", "logfx_get_option", "logfx_tune"]
+           "logfx_set_option", "logfx_get_option", "logfx_tune",
+           "logfx_gate_features", "logfx_gate_set_params", "logfx_gate_get_params",
+           "logfx_gate_load", "logfx_gate_save", "logfx_gate_forward", "logfx_gate_backward",
+           "logfx_gate_step", "logfx_gate"]
+GATE_NPARAM, GATE_CELLS, GATE_MAX_BATCH = 14369, 128, 4096
 OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH = 1, 2, 3, 4
 
 
@@ -60,12 +64,16 @@ class logfx_report(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("sigma_g", ctypes.c_double * 2),
                 ("thresh", ctypes.c_double * 2), ("zc_count", ctypes.c_int64 * 2),
                 ("extracted", ctypes.c_int64), ("output", ctypes.c_int64),
-                ("path", ctypes.c_int32), ("smoothed", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("smoothed", ctypes.c_int32),
+                ("gated", ctypes.c_int32), ("gate_fallback", ctypes.c_int32),
+                ("gate_logit", ctypes.c_double)]
 
     def as_dict(self):
         return {"pixels": self.pixels, "sigma_g": list(self.sigma_g), "thresh": list(self.thresh),
                 "zc_count": list(self.zc_count), "extracted": self.extracted,
-                "output": self.output, "path": self.path, "smoothed": self.smoothed}
+                "output": self.output, "path": self.path, "smoothed": self.smoothed,
+                "gated": self.gated, "gate_fallback": self.gate_fallback,
+                "gate_logit": self.gate_logit}
 
 
 _lib = None
@@ -124,6 +132,20 @@ def load(path: str | None = None):
     lib.logfx_timing_read.restype = ctypes.c_int
     lib.logfx_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]
+    IMGS, PAR = ctypes.POINTER(logfx_image), ctypes.POINTER(logfx_params)
+    FP = ctypes.POINTER(ctypes.c_float)
+    for name, args in [
+            ("logfx_gate_features", [P, ctypes.c_int32, IMGS, PAR, P, P]),
+            ("logfx_gate_set_params", [P, FP, ctypes.c_int64]),
+            ("logfx_gate_get_params", [P, FP, ctypes.c_int64]),
+            ("logfx_gate_load", [P, ctypes.c_char_p]),
+            ("logfx_gate_save", [P, ctypes.c_char_p]),
+            ("logfx_gate_forward", [P, ctypes.c_int32, P, P, P, P]),
+            ("logfx_gate_backward", [P, ctypes.c_int32, P, P, P, P, P, P]),
+            ("logfx_gate_step", [P, P, ctypes.c_double, P]),
+            ("logfx_gate", [P, ctypes.c_int32, IMGS, PAR, P, P, P])]:
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = args
     _lib = lib
     return lib
 
@@ -168,7 +190,8 @@ class Params:
         p.std_mode = std_mode
         p.std_k = std_k
         p.std5_max = std5_max
-        p.smooth = SMOOTH_ALWAYS if smooth else SMOOTH_NEVER
+        # True / False, or one of SMOOTH_NEVER / SMOOTH_ALWAYS / SMOOTH_GATE
+        p.smooth = smooth if not isinstance(smooth, bool) else (SMOOTH_ALWAYS if smooth else SMOOTH_NEVER)
         p.median_size = median_size
         p.flags = flags
         self.c = p
@@ -317,3 +340,87 @@ class Context:
                                          *ptr, _stream_ptr(stream))
         _check(rc, self.ptr)
         return outs
+
+    # ------------------------------------------------------------ gate
+    def _descs(self, imgs, bits):
+        imgs = list(imgs) if isinstance(imgs, (list, tuple)) else [imgs]
+        return imgs, (logfx_image * len(imgs))(*[image(t, bits) for t in imgs])
+
+    def gate_features(self, imgs, params: Params, feats=None, *, bits: int = 0, stream=None):
+        """logfx_gate_features: bfloat16 features [n, 3, 128, 128] on the device."""
+        import torch
+        imgs, descs = self._descs(imgs, bits)
+        n = len(imgs)
+        if feats is None:
+            feats = torch.empty((n, 3, GATE_CELLS, GATE_CELLS), dtype=torch.bfloat16, device=imgs[0].device)
+        rc = self.lib.logfx_gate_features(self.ptr, n, descs, ctypes.byref(params.c),
+                                          ctypes.c_void_p(feats.data_ptr()), _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return feats
+
+    def gate_set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(self.lib.logfx_gate_set_params(self.ptr, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                              t.size), self.ptr)
+
+    def gate_get_params(self):
+        t = np.zeros(GATE_NPARAM, np.float32)
+        _check(self.lib.logfx_gate_get_params(self.ptr, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                              t.size), self.ptr)
+        return t
+
+    def gate_load(self, path: str):
+        _check(self.lib.logfx_gate_load(self.ptr, os.fsencode(path)), self.ptr)
+
+    def gate_save(self, path: str):
+        _check(self.lib.logfx_gate_save(self.ptr, os.fsencode(path)), self.ptr)
+
+    @staticmethod
+    def _batch(feats, idx, B):
+        if idx is not None:
+            return int(idx.numel()), ctypes.c_void_p(idx.data_ptr())
+        return int(B if B is not None else feats.shape[0]), None
+
+    def gate_forward(self, feats, idx=None, *, B=None, logits=None, stream=None):
+        """Logits of the samples (all of feats, the first B, or feats[idx])."""
+        import torch
+        nb, ip = self._batch(feats, idx, B)
+        if logits is None:
+            logits = torch.empty(nb, dtype=torch.float32, device=feats.device)
+        rc = self.lib.logfx_gate_forward(self.ptr, nb, ctypes.c_void_p(feats.data_ptr()), ip,
+                                         ctypes.c_void_p(logits.data_ptr()), _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return logits
+
+    def gate_backward(self, feats, labels, idx=None, *, B=None, grad=None, loss=None, stream=None):
+        """(gradient [GATE_NPARAM], mean loss [1]) as device float tensors.
+        grad=False leaves the gradient in the context's buffer for gate_step."""
+        import torch
+        nb, ip = self._batch(feats, idx, B)
+        if grad is None:
+            grad = torch.empty(GATE_NPARAM, dtype=torch.float32, device=feats.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        gp = None if grad is False else ctypes.c_void_p(grad.data_ptr())
+        rc = self.lib.logfx_gate_backward(self.ptr, nb, ctypes.c_void_p(feats.data_ptr()), ip,
+                                          ctypes.c_void_p(labels.data_ptr()), gp,
+                                          ctypes.c_void_p(loss.data_ptr()), _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return (None if grad is False else grad), loss
+
+    def gate_step(self, lr: float, grad=None, *, stream=None):
+        gp = None if grad is None else ctypes.c_void_p(grad.data_ptr())
+        _check(self.lib.logfx_gate_step(self.ptr, gp, float(lr), _stream_ptr(stream)), self.ptr)
+
+    def gate(self, imgs, params: Params, *, bits: int = 0, stream=None):
+        """logfx_gate: (logits float [n], decisions uint8 [n]) device tensors."""
+        import torch
+        imgs, descs = self._descs(imgs, bits)
+        n = len(imgs)
+        logits = torch.empty(n, dtype=torch.float32, device=imgs[0].device)
+        dec = torch.empty(n, dtype=torch.uint8, device=imgs[0].device)
+        rc = self.lib.logfx_gate(self.ptr, n, descs, ctypes.byref(params.c),
+                                 ctypes.c_void_p(logits.data_ptr()), ctypes.c_void_p(dec.data_ptr()),
+                                 _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return logits, dec

@@ -147,11 +147,12 @@ def config3(n: int = 64, seed: int = 3, base_seed: int = 3000, lo: int = 256, hi
     return tiles
 
 
-def gate_tile(index: int, size: int = 512, base_seed: int = 400000):
+def gate_tile(index: int, size: int = 512, base_seed: int = 400000, twin: bool = True):
     """One training tile of the smoothing gate and its noise-free twin: the
     8192^2 generator's density of rectangles and polylines on a size^2 11-bit
     tile, Gaussian noise sigma ~ U[0, 20] and salt-and-pepper density
-    ~ U[0, 0.2].  Returns (noisy, clean, sigma, density)."""
+    ~ U[0, 0.2].  Returns (noisy, clean, sigma, density); clean is None when
+    twin is False."""
     rng = np.random.default_rng(base_seed + index)
     sigma = float(rng.uniform(0.0, 20.0))
     density = float(rng.uniform(0.0, 0.2))
@@ -159,9 +160,48 @@ def gate_tile(index: int, size: int = 512, base_seed: int = 400000):
     kw = dict(n_rect=max(1, round(20000 * scale)), n_poly=max(1, round(500 * scale)), bits=11)
     seed = base_seed + 1_000_000 + index
     noisy = panchromatic(size, size, seed, noise_sigma=sigma, sp_density=density, **kw)
-    clean = panchromatic(size, size, seed, noise_sigma=0.0, sp_density=0.0, **kw)
+    clean = panchromatic(size, size, seed, noise_sigma=0.0, sp_density=0.0, **kw) if twin else None
     return noisy, clean, sigma, density
 
 
 def sha256(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+# Four-band workload of the gated pipeline: 16384^2 bands cut into 2048^2
+# tiles.  One noise-free base scene (the 8192^2 generator at four times the
+# area); band b is round(gain_b * base + offset_b), clipped to 11 bits; each
+# (band, tile) gets its own Gaussian noise sigma ~ U[0, 20] and salt-and-
+# pepper density ~ U[0, 0.2], so that smoothing helps some tiles and not
+# others.
+C5_GAIN = (0.9, 1.0, 1.1, 0.7)
+C5_OFFSET = (0.0, 40.0, -40.0, 80.0)
+
+
+def config5_base(size: int = 16384, seed: int = 5) -> np.ndarray:
+    scale = size * size / float(8192 * 8192)
+    return panchromatic(size, size, seed, n_rect=round(20000 * scale), n_poly=round(500 * scale),
+                        noise_sigma=0.0, sp_density=0.0, bits=11)
+
+
+def config5_tile(base: np.ndarray, band: int, ty: int, tx: int, tile: int = 2048, seed: int = 5):
+    """(noisy, clean, sigma, density) of tile (ty, tx) of band `band`."""
+    maxv = 2047
+    rng = np.random.default_rng([seed, band, ty, tx])
+    sigma = float(rng.uniform(0.0, 20.0))
+    density = float(rng.uniform(0.0, 0.2))
+    b = base[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile].astype(np.float64)
+    clean = np.clip(np.rint(C5_GAIN[band] * b + C5_OFFSET[band]), 0, maxv)
+    img = clean + rng.normal(0.0, sigma, size=clean.shape) if sigma > 0 else clean.copy()
+    np.rint(img, out=img)
+    np.clip(img, 0, maxv, out=img)
+    u = rng.random(img.shape)
+    img[u < density / 2] = 0
+    img[(u >= density / 2) & (u < density)] = maxv
+    return img.astype(np.uint16), clean.astype(np.uint16), sigma, density
+
+
+def config5_index(size: int = 16384, tile: int = 2048, bands: int = 4):
+    """(band, ty, tx) of every tile, in order."""
+    n = size // tile
+    return [(b, ty, tx) for b in range(bands) for ty in range(n) for tx in range(n)]

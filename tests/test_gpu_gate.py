@@ -1,0 +1,292 @@
+"""GPU parity of the smoothing gate against its FP64 oracle (oracle/gate.py):
+features gathered by pass 1, the network's logits, its gradients, the AdamW
+step, training, and the gated pipeline.
+
+Tolerances.  Features are exact cell sums on both sides, divided in the same
+order in FP64 and rounded once to bfloat16: bit-equal.  The network
+accumulates in FP32 on the matrix cores where the oracle uses FP64, and both
+round every stored activation to bfloat16; a value within ~1e-6 relative of
+a bfloat16 rounding boundary may round the other way (one bfloat16 step,
+2^-8 relative, on about 3 in 10^4 values).  Averaged by the pooling this
+moves a logit by ~1e-4 at most in these cases: logits must agree within
+1e-3 (relative, with 1e-3 absolute floor), and a decision may differ only
+where |logit| < 1e-3.  Gradients see the flips directly (they are not
+averaged before the weight products): per parameter tensor the relative L2
+error must stay below 1e-2.  The AdamW step is FP32 against FP64 on the
+same gradient: 1e-5 relative."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import gate as og
+from paper_1304_3992_amd import logfx, scenes
+from parity import masks, run_oracle, to_device
+
+pytestmark = pytest.mark.gpu
+
+LOGIT_TOL = 1e-3
+GRAD_REL_L2 = 1e-2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = logfx.Context(0)
+    yield c
+    c.close()
+
+
+def _bf16_dev(x):
+    """Seeded FP64 values to a device bfloat16 tensor (round to nearest even)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(torch.bfloat16).cuda()
+
+
+def _features_cases():
+    rng = np.random.default_rng(71)
+    return [
+        ("scene_u11_512", scenes.gate_tile(3)[0], 11),
+        ("scene_u11_ragged", scenes.panchromatic(301, 517, 72, n_rect=60, n_poly=4, noise_sigma=9.0,
+                                                 sp_density=0.03, bits=11), 11),
+        ("u8_small", rng.integers(0, 256, (100, 77)).astype(np.uint8), 8),
+        ("u8_tall", scenes.config1()[:, :40], 8),
+        ("u16_fp64", rng.integers(0, 65536, (150, 260)).astype(np.uint16), 16),
+        ("one_pixel", np.array([[9]], np.uint8), 8),
+    ]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_features_bit_exact(ctx, case):
+    """Pass-1 cell sums -> bfloat16 features equal the oracle's features of
+    the oracle's crossing maps, value for value (single-image calls)."""
+    import torch
+    name, img, bits = _features_cases()[case]
+    orc_t, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    f = ctx.gate_features(to_device(img), params, bits=bits)
+    torch.cuda.synchronize()
+    got = f.float().cpu().numpy().astype(np.float64)[0]
+    o = run_oracle(img, orc_t)
+    ref = og.bf16(og.features(img, o["Z1"], o["Z2"], bits))
+    bad = np.argwhere(got != ref)
+    assert bad.size == 0, (name, bad[:5], got[tuple(bad[0])], ref[tuple(bad[0])])
+
+
+def test_features_batch_equals_singles(ctx):
+    """A batch of uneven tiles (several pass-1 tiles per image, several
+    images per launch) gives each image its single-call features."""
+    import torch
+    tiles = scenes.config3(n=7, seed=73, base_seed=7300, lo=60, hi=900)
+    _, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    devs = [to_device(t) for t in tiles]
+    fb = ctx.gate_features(devs, params, bits=8)
+    singles = [ctx.gate_features(d, params, bits=8) for d in devs]
+    torch.cuda.synchronize()
+    for i, s in enumerate(singles):
+        assert torch.equal(fb[i], s[0]), i
+
+
+def _net_inputs(B, seed):
+    rng = np.random.default_rng(seed)
+    feats = rng.random((B, 3, 128, 128))
+    feats[:, 1:] *= 0.6
+    theta = og.init(seed)
+    labels = (rng.random(B) < 0.5).astype(np.float64)
+    return feats, theta, labels
+
+
+@pytest.mark.parametrize("B,seed", [(1, 81), (5, 82), (19, 83)])
+def test_forward_logits(ctx, B, seed):
+    import torch
+    feats, theta, _ = _net_inputs(B, seed)
+    ctx.gate_set_params(theta)
+    z = ctx.gate_forward(_bf16_dev(feats)).cpu().numpy().astype(np.float64)
+    z_ref, _ = og.forward(theta, feats)
+    np.testing.assert_allclose(z, z_ref, rtol=LOGIT_TOL, atol=LOGIT_TOL)
+
+
+def test_forward_through_sample_indices(ctx):
+    import torch
+    feats, theta, _ = _net_inputs(12, 84)
+    ctx.gate_set_params(theta)
+    idx = torch.tensor([7, 0, 11, 7, 3], dtype=torch.int32, device="cuda")
+    z = ctx.gate_forward(_bf16_dev(feats), idx).cpu().numpy().astype(np.float64)
+    z_ref, _ = og.forward(theta, feats[[7, 0, 11, 7, 3]])
+    np.testing.assert_allclose(z, z_ref, rtol=LOGIT_TOL, atol=LOGIT_TOL)
+
+
+@pytest.mark.parametrize("B,seed", [(2, 91), (9, 92)])
+def test_gradient_matches_oracle(ctx, B, seed):
+    import torch
+    feats, theta, labels = _net_inputs(B, seed)
+    theta[og.NPARAM - 1] = 0.3
+    ctx.gate_set_params(theta)
+    lab = torch.tensor(labels, dtype=torch.float32, device="cuda")
+    g, loss = ctx.gate_backward(_bf16_dev(feats), lab)
+    g = g.cpu().numpy().astype(np.float64)
+    loss_ref, g_ref = og.backward(theta, feats, labels)
+    assert float(loss.cpu()[0]) == pytest.approx(loss_ref, rel=1e-4, abs=1e-5)
+    o = 0
+    for name, shape in og.SHAPES:
+        n = int(np.prod(shape))
+        a, r = g[o:o + n], g_ref[o:o + n]
+        err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+        assert err < GRAD_REL_L2, (name, err)
+        o += n
+
+
+def test_adamw_step_matches_oracle(ctx):
+    """Three AdamW steps on given gradients: FP32 on the GPU, FP64 in the
+    oracle, same formula."""
+    import torch
+    rng = np.random.default_rng(95)
+    theta = og.init(95)
+    ctx.gate_set_params(theta)
+    m = np.zeros(og.NPARAM)
+    v = np.zeros(og.NPARAM)
+    th = theta.copy()
+    for step in range(1, 4):
+        gr = rng.normal(0, 1e-2, og.NPARAM).astype(np.float32).astype(np.float64)
+        ctx.gate_step(3e-3, torch.tensor(gr, dtype=torch.float32, device="cuda"))
+        th, m, v = og.adamw(th, gr, m, v, step, 3e-3)
+    got = ctx.gate_get_params().astype(np.float64)
+    np.testing.assert_allclose(got, th, rtol=1e-5, atol=1e-7)
+
+
+def test_parameters_round_trip_file(ctx, tmp_path):
+    theta = og.init(96).astype(np.float32)
+    ctx.gate_set_params(theta)
+    p = str(tmp_path / "gate.bin")
+    ctx.gate_save(p)
+    with logfx.Context(0) as c2:
+        c2.gate_load(p)
+        assert np.array_equal(c2.gate_get_params(), theta)
+    with open(p, "r+b") as f:
+        f.write(b"XXXX")
+    with logfx.Context(0) as c3:
+        with pytest.raises(logfx.LogfxError) as e:
+            c3.gate_load(p)
+        assert e.value.code == logfx.EINVAL
+
+
+def test_training_reduces_loss_deterministically(ctx):
+    """Steps of backward + AdamW on a separable synthetic task: the loss
+    falls, the accuracy rises, and two runs from the same start give the
+    same parameters bit for bit (fixed-order reductions)."""
+    import torch
+    rng = np.random.default_rng(97)
+    N = 256
+    feats = rng.random((N, 3, 128, 128)) * 0.2
+    y = (rng.random(N) < 0.5)
+    feats[y, 1] += 0.5            # the positives have dense mask-1 crossings
+    fd = _bf16_dev(feats)
+    lab = torch.tensor(y.astype(np.float32), device="cuda")
+    theta0 = og.init(98)
+
+    def train():
+        ctx.gate_set_params(theta0)
+        losses = []
+        g = torch.empty(og.NPARAM, dtype=torch.float32, device="cuda")
+        for it in range(40):
+            idx = torch.from_numpy(np.random.default_rng(it).choice(N, 64, replace=False).astype(np.int32)).cuda()
+            _, loss = ctx.gate_backward(fd, lab, idx, grad=g)
+            ctx.gate_step(3e-3, g)
+            losses.append(float(loss.cpu()[0]))
+        return losses, ctx.gate_get_params()
+
+    l1, p1 = train()
+    l2, p2 = train()
+    assert np.array_equal(p1, p2)
+    assert l1 == l2
+    assert np.mean(l1[-5:]) < 0.5 * np.mean(l1[:5]), l1
+    z = ctx.gate_forward(fd).cpu().numpy()
+    assert ((z > 0) == y).mean() > 0.95
+
+
+def _gate_tiles():
+    out = []
+    for i in range(6):
+        noisy, _, _, _ = scenes.gate_tile(10_000 + i, size=256 + 64 * i)
+        out.append(noisy)
+    return out
+
+
+def test_gated_pipeline_against_oracle_chain(ctx):
+    """SMOOTH_GATE on a batch: every image's decision equals the oracle
+    chain's (oracle maps -> oracle features -> oracle network) unless its
+    logit lies within the tolerance of 0, and its output equals the
+    oracle's smoothed or unsmoothed map accordingly (band rule)."""
+    import torch
+    from parity import compare
+    tiles = _gate_tiles()
+    orc_t, lib_t = masks()
+    theta = og.init(99)
+    theta[og.NPARAM - 1] = 0.0
+    ctx.gate_set_params(theta)
+    params = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE)
+    devs = [to_device(t) for t in tiles]
+    outs, reps = ctx.extract_batch(devs, params, bits=11, report=True)
+    logits, dec = ctx.gate(devs, params, bits=11)
+    torch.cuda.synchronize()
+    logits = logits.cpu().numpy()
+    dec = dec.cpu().numpy()
+    feats = []
+    orcs = []
+    for t in tiles:
+        o = run_oracle(t, orc_t, smooth=True)
+        orcs.append(o)
+        feats.append(og.features(t, o["Z1"], o["Z2"], 11))
+    z_ref, _ = og.forward(theta, np.stack(feats))
+    for i, t in enumerate(tiles):
+        r = reps[i]
+        assert r["gated"] == 1 and r["gate_fallback"] == 0
+        assert r["gate_logit"] == pytest.approx(float(logits[i]), abs=0)
+        assert abs(logits[i] - z_ref[i]) <= LOGIT_TOL * (1 + abs(z_ref[i])), (i, logits[i], z_ref[i])
+        if abs(z_ref[i]) > LOGIT_TOL:
+            assert r["smoothed"] == int(z_ref[i] > 0), i
+        assert dec[i] == r["smoothed"]
+        o = orcs[i]
+        ref = o if r["smoothed"] else {**o, "F": o["E"]}
+        compare(outs[i].cpu().numpy(), ref, smooth=bool(r["smoothed"]))
+
+
+def test_gate_bias_forces_each_choice_and_fallback(ctx):
+    """With a large positive (negative) output bias every image is smoothed
+    (not smoothed): the gated batch equals the ALWAYS (NEVER) batch bit for
+    bit.  With no parameters in a context GATE falls back to ALWAYS and
+    reports it."""
+    import torch
+    tiles = _gate_tiles()[:4]
+    _, lib_t = masks()
+    devs = [to_device(t) for t in tiles]
+    always = ctx.extract_batch(devs, logfx.Params(*lib_t, smooth=True), bits=11)
+    never = ctx.extract_batch(devs, logfx.Params(*lib_t, smooth=False), bits=11)
+    gparams = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE)
+    theta = og.init(100)
+    for bias, ref, flag in ((50.0, always, 1), (-50.0, never, 0)):
+        theta[og.NPARAM - 1] = bias
+        ctx.gate_set_params(theta)
+        for graph in (1, 0):
+            ctx.set_option(logfx.OPT_GRAPH, graph)
+            outs, reps = ctx.extract_batch(devs, gparams, bits=11, report=True)
+            torch.cuda.synchronize()
+            for o, r, e in zip(outs, reps, ref):
+                assert torch.equal(o, e)
+                assert r["smoothed"] == flag and r["gated"] == 1
+        ctx.set_option(logfx.OPT_GRAPH, 1)
+        single, rep = ctx.extract(devs[0], gparams, bits=11, report=True)
+        assert torch.equal(single, ref[0]) and rep["smoothed"] == flag
+    with logfx.Context(0) as fresh:
+        outs, reps = fresh.extract_batch(devs, gparams, bits=11, report=True)
+        torch.cuda.synchronize()
+        for o, r, e in zip(outs, reps, always):
+            assert torch.equal(o, e)
+            assert r["gate_fallback"] == 1 and r["gated"] == 0 and r["smoothed"] == 1
+        with pytest.raises(logfx.LogfxError) as e:
+            fresh.gate(devs, gparams, bits=11)
+        assert e.value.code == logfx.EINVAL
