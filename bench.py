@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (strip heights stay at their defaults)")
+    ap.add_argument("--store-z", type=int, default=1, choices=[0, 1],
+                    help="1: pass 2 reads the strengths pass 1 stored (default); 0: recomputes them")
     ap.add_argument("--workload", choices=["scene", "gated"], default="scene",
                     help="scene: the 8192^2 scene (default); gated: the gate's four-band workload")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -240,6 +242,7 @@ def main():
     bufs = [host.to(dev) for _ in range(3)]
     out = torch.empty((H, W), dtype=torch.uint8, device=dev)
     ctx = logfx.Context(0)
+    ctx.set_option(logfx.OPT_STORE_Z, args.store_z)
     stream = torch.cuda.current_stream()
 
     tuned = None
@@ -301,7 +304,7 @@ def main():
         "config": {"workload": f"{H}x{W} uint16 11-bit scene (20000 rectangles, 500 polylines, "
                                "noise sigma 12, 5% salt-and-pepper); LoG 5x5 s0.8 + 9x9 s1.4; "
                                "3x3 deviation > 2.0 global; 5x5 hybrid median",
-                   "pixels": px, "parallelism": "single GPU",
+                   "pixels": px, "parallelism": "single GPU", "store_z": args.store_z,
                    "rows_per_strip": [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]},
         "kernels_ms": {"pass1": round(avg[0], 4), "finalize": round(avg[1], 4),
                        "pass2": round(avg[2], 4)},

@@ -190,7 +190,12 @@ enum {
     LOGFX_OPT_ROWS1 = 1,      /* output rows per wave strip in pass 1 (1..1024, default 64) */
     LOGFX_OPT_ROWS2 = 2,      /* the same for pass 2 (default 64) */
     LOGFX_OPT_PERSISTENT = 3, /* batches: 1 = persistent launch, 0 = one workgroup per tile (default) */
-    LOGFX_OPT_GRAPH = 4       /* batches: 1 = replay a captured hipGraph (default), 0 = direct launches */
+    LOGFX_OPT_GRAPH = 4,      /* batches: 1 = replay a captured hipGraph (default), 0 = direct launches */
+    LOGFX_OPT_STORE_Z = 5     /* 1 (default) = pass 1 stores the crossing strengths of every pixel in
+                                 context memory (8 bytes per pixel on the integer path, 16 on FP64) and
+                                 pass 2 reads them; 0 = pass 2 recomputes them from the image (no such
+                                 memory).  Both give the same output; a call whose strength memory
+                                 cannot be allocated recomputes. */
 };
 int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value);
 int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value);

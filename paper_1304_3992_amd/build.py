@@ -29,7 +29,8 @@ def _units():
     b = os.path.join(HERE, "_build")
     units = [("logfx_host.cpp", os.path.join(b, "logfx_host.o"), []),
              ("logfx_dispatch.hip", os.path.join(b, "logfx_dispatch.o"), ["-x", "hip"]),
-             ("logfx_gate.hip", os.path.join(b, "logfx_gate.o"), ["-x", "hip"])]
+             ("logfx_gate.hip", os.path.join(b, "logfx_gate.o"), ["-x", "hip"]),
+             ("logfx_pass2z.hip", os.path.join(b, "logfx_pass2z.o"), ["-x", "hip"])]
     for ra, rb in RADII:
         units.append(("logfx_kernels_inst.hip", os.path.join(b, f"logfx_kernels_r{ra}{rb}.o"),
                       ["-x", "hip", f"-DLOGFX_RA={ra}", f"-DLOGFX_RB={rb}"]))

@@ -53,6 +53,9 @@ struct logfx_ctx {
     TileCfg tiles;
     bool persistent = false;         // batches: one resident grid walks all tiles
     bool graph = true;               // batches: replay a captured hipGraph
+    bool store_z = true;             // pass 1 stores the strengths, pass 2 reads them
+    void *zmap = nullptr;            // strength pairs of the images of a call
+    long long zcap = 0;              // bytes
     // device scratch
     double *partials = nullptr;      // [cap1][4]
     long long *counts1 = nullptr;    // [cap1][2]
@@ -426,17 +429,17 @@ struct ImageTiles {
     int tiles_x1, ntiles1, tiles_x2, ntiles2;
 };
 
-int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, ImageTiles &t) {
+int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, bool storez, ImageTiles &t) {
     const TileCfg &c = ctx->tiles;
     const long long H = img->height, W = img->width;
     if (H >= (1LL << 30) || W >= (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image sides must be below 2^30");
-    const long long tw1 = tile_out_width(kHalo1), tw2 = tile_out_width(kHalo2);
+    const long long tw1 = tile_out_width(kHalo1), tw2 = tile_out_width(storez ? kHalo2Z : kHalo2);
     const long long tx1 = (W + tw1 - 1) / tw1, ty1 = (H + c.rows1 - 1) / c.rows1;
     const long long tx2 = (W + tw2 - 1) / tw2, ty2 = (H + c.rows2 - 1) / c.rows2;
     if (tx1 * ty1 > (1LL << 30) || tx2 * ty2 > (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image too large for one launch");
-    if (lds_bytes(c.rows1, kHalo1, pl.rb) > 65536 || lds_bytes(c.rows2, kHalo2, pl.rb) > 65536)
+    if (lds_bytes(c.rows1, kHalo1, pl.rb) > 65536 || (!storez && lds_bytes(c.rows2, kHalo2, pl.rb) > 65536))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "tile configuration exceeds 64 KiB of LDS");
     t.tiles_x1 = (int)tx1, t.ntiles1 = (int)(tx1 * ty1);
     t.tiles_x2 = (int)tx2, t.ntiles2 = (int)(tx2 * ty2);
@@ -467,8 +470,26 @@ struct Call {
     Plan pl;
     Launch L;
     int n = 1;
+    bool storez = false;   // pass 1 stores the strengths in ctx->zmap, pass 2 reads them
     std::vector<ImageTiles> tiles;
 };
+
+// Device memory for the strength pairs of `px` pixels; false if it cannot
+// be had (the call then recomputes the strengths in pass 2).
+bool ensure_zmap(logfx_ctx *ctx, long long px, int path) {
+    const long long bytes = px * (path == LOGFX_PATH_INT32 ? 8 : 16);
+    if (bytes <= ctx->zcap) return true;
+    (void)hipFree(ctx->zmap);
+    ctx->zmap = nullptr;
+    ctx->zcap = 0;
+    if (hipMalloc(&ctx->zmap, (size_t)bytes) != hipSuccess) {
+        ctx->zmap = nullptr;
+        (void)hipGetLastError();   // clear the sticky out-of-memory error
+        return false;
+    }
+    ctx->zcap = bytes;
+    return true;
+}
 
 // Validates the images against the parameters, tiles them and (for a batch)
 // uploads the image table and tile owners.
@@ -477,6 +498,14 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
     if (n < 1 || !imgs) return set_err(ctx, LOGFX_EINVAL, "no images");
     int rc = check_all(ctx, &imgs[0], p, c.pl);
     if (rc != LOGFX_OK) return rc;
+    // strengths are stored between the passes when the context allows it and
+    // the memory for them can be had
+    c.storez = false;
+    if (need_out && ctx->store_z) {
+        long long px = 0;
+        for (int i = 0; i < n; ++i) px += (long long)imgs[i].height * imgs[i].width;
+        c.storez = ensure_zmap(ctx, px, c.pl.path);
+    }
     const int bits0 = imgs[0].bits == 0 ? (imgs[0].dtype == LOGFX_U8 ? 8 : 16) : imgs[0].bits;
     c.n = n;
     c.tiles.resize(n);
@@ -491,7 +520,7 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
                                                   "dtype and bits", i);
         }
         if (need_out && (!outs || !outs[i])) return set_err(ctx, LOGFX_EINVAL, "output %d is NULL", i);
-        if ((rc = tile_image(ctx, &imgs[i], c.pl, c.tiles[i])) != LOGFX_OK) return rc;
+        if ((rc = tile_image(ctx, &imgs[i], c.pl, c.storez, c.tiles[i])) != LOGFX_OK) return rc;
         t1 += c.tiles[i].ntiles1;
         t2 += c.tiles[i].ntiles2;
     }
@@ -502,9 +531,12 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
     c.L.nimg = n;
     c.L.total1 = (int)t1;
     c.L.total2 = (int)t2;
+    long long zoff = 0;
     auto job = [&](int i, int b1, int b2) {
         ImageJob j;
         std::memset(&j, 0, sizeof j);
+        j.zoff = zoff;
+        zoff += imgs[i].height * imgs[i].width;
         j.img = image_desc(&imgs[i]);
         j.out = outs ? outs[i] : nullptr;
         j.out_pitch = imgs[i].width;
@@ -568,6 +600,7 @@ struct Launches {
     int grid1, grid2;
     int path, ra, rb;
     bool dbg;
+    bool storez;
     // smoothing gate
     bool features;                 // pass 1 sums the cells; the features are finished after it
     bool gated;                    // the network decides the median per image before pass 2
@@ -607,13 +640,17 @@ void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *con
     a2.stats = ctx->stats;
     a2.counts = ctx->counts2;
     a2.smooth = p->smooth != LOGFX_SMOOTH_NEVER;   // GATE without a gate falls back to ALWAYS
+    if (c.storez) {
+        a1.zmap = ctx->zmap;
+        a2.zmap = ctx->zmap;
+    }
     a2.median_size = p->median_size;
 }
 
 hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int until) {
     hipError_t e;
     const bool i32 = k.path == LOGFX_PATH_INT32;
-    const int mode = k.dbg ? 1 : k.features ? 2 : 0;
+    const int mode = (k.dbg ? kP1Maps : 0) | (k.features ? kP1Cells : 0) | (k.storez ? kP1StoreZ : 0);
     if (k.features && (e = gate::launch_zero_cells(k.cells, k.fin.L.nimg, s)) != hipSuccess) return e;
     e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, mode, k.grid1, s)
             : launch_pass1_d(k.ra, k.rb, k.p1.d, mode, k.grid1, s);
@@ -633,6 +670,7 @@ hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int unti
             return e;
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    if (k.storez) return i32 ? launch_pass2z_i(k.p2.i, k.grid2, s) : launch_pass2z_d(k.p2.d, k.grid2, s);
     return i32 ? launch_pass2_i(k.ra, k.rb, k.p2.i, k.grid2, s)
                : launch_pass2_d(k.ra, k.rb, k.p2.d, k.grid2, s);
 }
@@ -658,6 +696,7 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
     k.path = c.pl.path;
     k.ra = c.pl.ra;
     k.rb = c.pl.rb;
+    k.storez = c.storez;
     if (k.path == LOGFX_PATH_INT32) fill_args<OrbitTapsI, int>(c, ctx, p, L, Z, k.p1.i, k.p2.i, k.dbg);
     else fill_args<OrbitTapsD, double>(c, ctx, p, L, Z, k.p1.d, k.p2.d, k.dbg);
     if (gate > 0) {
@@ -692,9 +731,12 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
         // a persistent launch: as many workgroups as fit on the device
         int m1 = 0, m2 = 0;
         const bool i32 = k.path == LOGFX_PATH_INT32;
-        hipError_t e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, false, 0, nullptr, &m1)
-                           : launch_pass1_d(k.ra, k.rb, k.p1.d, false, 0, nullptr, &m1);
-        if (e == hipSuccess)
+        const int mode = k.storez ? kP1StoreZ : 0;
+        hipError_t e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, mode, 0, nullptr, &m1)
+                           : launch_pass1_d(k.ra, k.rb, k.p1.d, mode, 0, nullptr, &m1);
+        if (e == hipSuccess && k.storez)
+            e = i32 ? launch_pass2z_i(k.p2.i, 0, nullptr, &m2) : launch_pass2z_d(k.p2.d, 0, nullptr, &m2);
+        else if (e == hipSuccess)
             e = i32 ? launch_pass2_i(k.ra, k.rb, k.p2.i, 0, nullptr, &m2)
                     : launch_pass2_d(k.ra, k.rb, k.p2.d, 0, nullptr, &m2);
         if (e != hipSuccess) return hip_err(ctx, e, "occupancy query");
@@ -961,6 +1003,7 @@ int logfx_destroy(logfx_ctx *ctx) {
             (void)hipEventSynchronize(ctx->staged);
             (void)hipEventDestroy(ctx->staged);
         }
+        (void)hipFree(ctx->zmap);
         (void)hipFree(ctx->partials);
         (void)hipFree(ctx->counts1);
         (void)hipFree(ctx->counts2);
@@ -1063,6 +1106,7 @@ int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value) {
         return LOGFX_OK;
     case LOGFX_OPT_PERSISTENT: ctx->persistent = value != 0; return LOGFX_OK;
     case LOGFX_OPT_GRAPH: ctx->graph = value != 0; return LOGFX_OK;
+    case LOGFX_OPT_STORE_Z: ctx->store_z = value != 0; return LOGFX_OK;
     default: return set_err(ctx, LOGFX_EINVAL, "unknown option %d", option);
     }
 }
@@ -1074,6 +1118,7 @@ int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value) {
     case LOGFX_OPT_ROWS2: *value = ctx->tiles.rows2; return LOGFX_OK;
     case LOGFX_OPT_PERSISTENT: *value = ctx->persistent; return LOGFX_OK;
     case LOGFX_OPT_GRAPH: *value = ctx->graph; return LOGFX_OK;
+    case LOGFX_OPT_STORE_Z: *value = ctx->store_z; return LOGFX_OK;
     default: return set_err(ctx, LOGFX_EINVAL, "unknown option %d", option);
     }
 }

@@ -17,6 +17,13 @@ constexpr int kMaxOrbits = (kMaxRadius + 1) * (kMaxRadius + 2) / 2;
 //  pass 2: median (+-2) <- local std (+-1) <- zero crossing (+-1) = +-4.
 constexpr int kHalo1 = 1;
 constexpr int kHalo2 = 4;
+//  pass 2 on stored strengths: median (+-2) <- local std (+-1) = +-3.
+constexpr int kHalo2Z = 3;
+
+// Pass-1 variants (bits of its MODE).
+constexpr int kP1Maps = 1;     // FP64 maps of L and Z (single images, for inspection)
+constexpr int kP1Cells = 2;    // the gate's per-cell sums
+constexpr int kP1StoreZ = 4;   // the (Z_1, Z_2) pair of every pixel for pass 2
 
 // Side of the cell grid over which pass 1 sums the smoothing gate's
 // features (kGateCells x kGateCells cells per image).
@@ -65,6 +72,7 @@ struct ImageJob {
     int tiles_x1, tiles_x2;  // tiles across the image in pass 1 / pass 2
     int base1, base2;        // index of the image's first tile among the launch's tiles
     int ntiles1, ntiles2;
+    long long zoff;          // first element of the image's strength pairs in the Z map (H*W of them)
 };
 
 // The work of one launch: one image (passed inline) or a batch of images
@@ -92,7 +100,10 @@ struct Pass1Args {
     double *dbgL[2];
     double *dbgZ[2];
     double unit[2];
-    // Gate features (mode 2): [nimg][2][kGateCells^2] counters, zeroed
+    // Strength pairs (kP1StoreZ): int2 (integer path) or double2 (FP64
+    // path) per pixel, image i at element jobs[i].zoff, row pitch W.
+    void *zmap;
+    // Gate features (kP1Cells): [nimg][2][kGateCells^2] counters, zeroed
     // before the launch; plane 0 sums pixel values, plane 1 sums
     // [Z_1 != 0] + 2^32 [Z_2 != 0] (every cell must hold < 2^32 pixels).
     unsigned long long *cells;
@@ -110,6 +121,7 @@ struct Pass2Args {
     int smooth;             // 0 = E, 1 = hybrid median of E
     int median_size;        // 3 or 5
     const int *med_flags;   // [nimg] or nullptr: when given, image i is smoothed iff med_flags[i] != 0
+    const void *zmap;       // strength pairs written by pass 1 (pass 2 on stored strengths)
 };
 
 struct FinalizeArgs {
@@ -127,8 +139,7 @@ struct FinalizeArgs {
 // workgroups (at most the number of tiles; fewer makes the launch
 // persistent).  max_grid, when non-null, receives the number of workgroups
 // that fit on the device at once and nothing is launched.
-// mode: 0 statistics only, 1 also the FP64 maps (dbgL / dbgZ), 2 also the
-// gate's cell sums (cells); modes 1 and 2 run one tile per workgroup.
+// mode: a set of kP1* bits; with kP1Maps or kP1Cells one tile per workgroup.
 hipError_t launch_pass1_i(int ra, int rb, const Pass1Args<OrbitTapsI> &a, int mode, int grid,
                           hipStream_t s, int *max_grid = nullptr);
 hipError_t launch_pass1_d(int ra, int rb, const Pass1Args<OrbitTapsD> &a, int mode, int grid,
@@ -138,6 +149,10 @@ hipError_t launch_pass2_i(int ra, int rb, const Pass2Args<OrbitTapsI> &a, int gr
 hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s,
                           int *max_grid = nullptr);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+// Pass 2 on the strengths stored by pass 1 (no LoG, no LDS): tiles of
+// tile_out_width(kHalo2Z) columns.
+hipError_t launch_pass2z_i(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s, int *max_grid = nullptr);
+hipError_t launch_pass2z_d(const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s, int *max_grid = nullptr);
 
 // LDS bytes of one workgroup.
 inline size_t lds_bytes(int rows, int halo, int rb) {

@@ -348,14 +348,41 @@ __device__ inline ImageJob job_of(const Launch &L, int image) {
     return L.nimg == 1 ? L.one : L.jobs[image];
 }
 
+// Storage of the crossing-strength pair of a pixel between the passes: the
+// integer path keeps the exact integer strengths as int32 pairs, the FP64
+// path as double pairs (LoG grid units either way).
+template <class Acc> struct ZStore;
+template <> struct ZStore<int> {
+    using T = int2;
+    __device__ static void put(void *m, long long at, const double (&z)[2]) {
+        static_cast<int2 *>(m)[at] = make_int2((int)z[0], (int)z[1]);
+    }
+    __device__ static void get(const T &v, double &z0, double &z1) {
+        z0 = (double)v.x;
+        z1 = (double)v.y;
+    }
+};
+template <> struct ZStore<double> {
+    using T = double2;
+    __device__ static void put(void *m, long long at, const double (&z)[2]) {
+        static_cast<double2 *>(m)[at] = make_double2(z[0], z[1]);
+    }
+    __device__ static void get(const T &v, double &z0, double &z1) {
+        z0 = v.x;
+        z1 = v.y;
+    }
+};
+
 // ------------------------------------------------------------- pass 1
 // Occupancy: the integer path is held to 128 VGPRs (4 waves per SIMD, the
 // LDS limit), which costs a few spills but measures faster than 3 waves; the
 // FP64 path keeps its registers.
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
 
-// MODE: 0 = statistics only; 1 = also the FP64 maps of a single image;
-// 2 = also the per-cell sums of the gate features.
+// MODE, a set of bits: 0 = statistics only; kP1Maps = also the FP64 maps
+// of a single image; kP1Cells = also the per-cell sums of the gate
+// features; kP1StoreZ = also the crossing-strength pair (Z_1, Z_2) of every
+// pixel, for pass 2 to read instead of recomputing it.
 template <class Acc, int RA, int RB, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
@@ -389,7 +416,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
     int fkey = 0, fcy = 0;      // this lane's cell column; current cell row
     long long fnext = 0;        // first row of the next cell row
     unsigned long long *fcells = nullptr;
-    if constexpr (MODE == 2) {
+    if constexpr ((MODE & kP1Cells) != 0) {
         fkey = g.outc ? (int)(((long long)g.xc * kGateCells) / g.W) : (g.lane < HL ? -1 : kGateCells);
         fcy = (int)(((long long)g.y0 * kGateCells) / g.H);
         fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) / kGateCells;
@@ -434,6 +461,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
         // zero crossings of row t - 1 (valid from the third step on)
         const int r = t - 1;
         const bool use = g.outc & (si >= 2);
+        double zr[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const Acc c = L[j][1];
@@ -444,8 +472,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
             sz[j] += zu;
             sq[j] = __fma_rn(zu, zu, sq[j]);
             cnt[j] += __popcll(__ballot(zu != 0.0));   // wave-uniform
-            if constexpr (MODE == 2) fc += (unsigned)(zu != 0.0) << (16 * j);
-            if constexpr (MODE == 1) {
+            if constexpr ((MODE & kP1Cells) != 0) fc += (unsigned)(zu != 0.0) << (16 * j);
+            if constexpr ((MODE & kP1StoreZ) != 0) zr[j] = z;
+            if constexpr ((MODE & kP1Maps) != 0) {
                 if (use) {
                     const long long at = (long long)r * g.W + g.xc;
                     if (a.dbgL[j]) a.dbgL[j][at] = AccOps<Acc>::to_d(c) * a.unit[j];
@@ -453,7 +482,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
                 }
             }
         }
-        if constexpr (MODE == 2) {
+        if constexpr ((MODE & kP1StoreZ) != 0) {
+            if (use) ZStore<Acc>::put(a.zmap, J.zoff + (long long)r * g.W + g.xc, zr);
+        }
+        if constexpr ((MODE & kP1Cells) != 0) {
             fv += use ? (unsigned)h[RB - 1][0] : 0u;   // pixel (r, xc)
             if (si >= 2 && (r + 1 == fnext || r == g.y0 + g.Rv - 1)) flush(r);
         }
@@ -654,18 +686,18 @@ template <class Acc, int RA, int RB, int MODE>
 hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
     const size_t shm = lds_bytes(a.rows, kHalo1, RB);
     // the map-writing and feature variants always run one tile per workgroup
-    if constexpr (MODE != 0) {
+    if constexpr ((MODE & (kP1Maps | kP1Cells)) != 0) {
         if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, false>, shm, max_grid);
         hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, false>), dim3(a.L.total1),
                            dim3(kTileWaves * kWave), shm, s, a);
         return hipGetLastError();
     }
-    if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, 0, true>, shm, max_grid);
+    if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, true>, shm, max_grid);
     if (grid >= a.L.total1)
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, 0, false>), dim3(a.L.total1),
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, false>), dim3(a.L.total1),
                            dim3(kTileWaves * kWave), shm, s, a);
     else
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, 0, true>), dim3(grid),
+        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, true>), dim3(grid),
                            dim3(kTileWaves * kWave), shm, s, a);
     return hipGetLastError();
 }

@@ -14,17 +14,27 @@
 
 namespace logfx {
 
+// Pass-1 variants built: statistics only, maps, cells, stored strengths,
+// stored strengths with cells.
+template <class Acc>
+hipError_t pass1_any(const Pass1Args<typename kern::AccOps<Acc>::Taps> &a, int mode, int grid, hipStream_t s,
+                     int *max_grid) {
+    switch (mode) {
+    case 0: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, 0>(a, grid, s, max_grid);
+    case kP1Maps: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1Maps>(a, grid, s, max_grid);
+    case kP1Cells: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1Cells>(a, grid, s, max_grid);
+    case kP1StoreZ: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1StoreZ>(a, grid, s, max_grid);
+    case kP1StoreZ | kP1Cells: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1StoreZ | kP1Cells>(a, grid, s, max_grid);
+    default: return hipErrorInvalidValue;
+    }
+}
 hipError_t LOGFX_FN(pass1_i)(const Pass1Args<OrbitTapsI> &a, int mode, int grid, hipStream_t s,
                              int *max_grid) {
-    if (mode == 1) return kern::p1<int, LOGFX_RA, LOGFX_RB, 1>(a, grid, s, max_grid);
-    if (mode == 2) return kern::p1<int, LOGFX_RA, LOGFX_RB, 2>(a, grid, s, max_grid);
-    return kern::p1<int, LOGFX_RA, LOGFX_RB, 0>(a, grid, s, max_grid);
+    return pass1_any<int>(a, mode, grid, s, max_grid);
 }
 hipError_t LOGFX_FN(pass1_d)(const Pass1Args<OrbitTapsD> &a, int mode, int grid, hipStream_t s,
                              int *max_grid) {
-    if (mode == 1) return kern::p1<double, LOGFX_RA, LOGFX_RB, 1>(a, grid, s, max_grid);
-    if (mode == 2) return kern::p1<double, LOGFX_RA, LOGFX_RB, 2>(a, grid, s, max_grid);
-    return kern::p1<double, LOGFX_RA, LOGFX_RB, 0>(a, grid, s, max_grid);
+    return pass1_any<double>(a, mode, grid, s, max_grid);
 }
 hipError_t LOGFX_FN(pass2_i)(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s, int *max_grid) {
     return kern::p2<int, LOGFX_RA, LOGFX_RB>(a, grid, s, max_grid);

@@ -29,7 +29,7 @@ EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_gate_load", "logfx_gate_save", "logfx_gate_forward", "logfx_gate_backward",
            "logfx_gate_step", "logfx_gate"]
 GATE_NPARAM, GATE_CELLS, GATE_MAX_BATCH = 14369, 128, 4096
-OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH = 1, 2, 3, 4
+OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH, OPT_STORE_Z = 1, 2, 3, 4, 5
 
 
 class LogfxError(RuntimeError):

@@ -185,3 +185,22 @@ def test_config2_full_size(ctx):
             assert np.array_equal(g[r0:r0 + 70].cpu().numpy(), o[k][r0:r0 + 70]), (k, r0)
     del maps
     print("config2", info)
+
+
+@pytest.mark.parametrize("name,make,bits,kw", [c for c in EXTRACT_CASES if c[0] in
+                                               ("c1", "c1_nosmooth", "c1_med3", "ragged_u11", "u16_fp64",
+                                                "tiny_1x1", "row_1x300", "col_300x1", "thin_3x500")],
+                         ids=lambda v: v if isinstance(v, str) else "")
+def test_stored_and_recomputed_strengths_agree(ctx, name, make, bits, kw):
+    """Pass 2 on the strengths stored by pass 1 and pass 2 recomputing them
+    from the image run the same FP64 operations: same bytes, same report."""
+    img = make()
+    _, lib_t = masks()
+    ctx.set_option(logfx.OPT_STORE_Z, 0)
+    try:
+        a, ra = run_gpu(ctx, img, lib_t, bits=bits, **kw)
+    finally:
+        ctx.set_option(logfx.OPT_STORE_Z, 1)
+    b, rb = run_gpu(ctx, img, lib_t, bits=bits, **kw)
+    assert np.array_equal(a, b)
+    assert ra == rb
