@@ -150,3 +150,40 @@ def test_create_without_device_fails_cleanly(lib):
     assert not ptr
     assert lib.logfx_extract(None, None, None, None, None, None) == logfx.EINVAL
     assert lib.logfx_destroy(None) == logfx.OK
+
+
+def test_gate_constants_and_smooth_modes(lib):
+    """The binding's gate constants match the header; GATE is a valid
+    smoothing choice for the argument checks."""
+    with open(os.path.join(ROOT, "include", "logfx.h")) as f:
+        text = f.read()
+    for name, val in (("LOGFX_GATE_NPARAM", logfx.GATE_NPARAM), ("LOGFX_GATE_CELLS", logfx.GATE_CELLS),
+                      ("LOGFX_GATE_MAX_BATCH", logfx.GATE_MAX_BATCH)):
+        assert re.search(rf"#define {name} {val}\b", text), name
+    assert re.search(r"LOGFX_SMOOTH_GATE = 2", text)
+    assert re.search(r"LOGFX_OPT_STORE_Z = 5", text) and logfx.OPT_STORE_Z == 5
+    from oracle import gate as og
+    assert og.NPARAM == logfx.GATE_NPARAM
+    p = _params()
+    p.c.smooth = logfx.SMOOTH_GATE
+    assert _rc(_img(), p) == (logfx.OK, logfx.PATH_INT32)
+
+
+def test_gate_entry_points_reject_null_context(lib):
+    """Every gate call returns EINVAL on a NULL context before it touches a
+    device."""
+    E = logfx.EINVAL
+    theta = np.zeros(logfx.GATE_NPARAM, np.float32)
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    p = _params()
+    im = _img()
+    assert lib.logfx_gate_features(None, 1, ctypes.byref(im), ctypes.byref(p.c), None, None) == E
+    assert lib.logfx_gate(None, 1, ctypes.byref(im), ctypes.byref(p.c), None, None, None) == E
+    assert lib.logfx_gate_set_params(None, tp, logfx.GATE_NPARAM) == E
+    assert lib.logfx_gate_get_params(None, tp, logfx.GATE_NPARAM) == E
+    assert lib.logfx_gate_load(None, b"/nonexistent") == E
+    assert lib.logfx_gate_save(None, b"/nonexistent") == E
+    assert lib.logfx_gate_forward(None, 1, None, None, None, None) == E
+    assert lib.logfx_gate_backward(None, 1, None, None, None, None, None, None) == E
+    assert lib.logfx_gate_step(None, None, 1e-3, None) == E
+    assert "ctx is NULL" in logfx.last_error()
