@@ -690,15 +690,15 @@ hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStrea
         if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, false>, shm, max_grid);
         hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, false>), dim3(a.L.total1),
                            dim3(kTileWaves * kWave), shm, s, a);
-        return hipGetLastError();
+    } else {
+        if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, true>, shm, max_grid);
+        if (grid >= a.L.total1)
+            hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, false>), dim3(a.L.total1),
+                               dim3(kTileWaves * kWave), shm, s, a);
+        else
+            hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, true>), dim3(grid),
+                               dim3(kTileWaves * kWave), shm, s, a);
     }
-    if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, true>, shm, max_grid);
-    if (grid >= a.L.total1)
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, false>), dim3(a.L.total1),
-                           dim3(kTileWaves * kWave), shm, s, a);
-    else
-        hipLaunchKernelGGL((pass1_kernel<Acc, RA, RB, MODE, true>), dim3(grid),
-                           dim3(kTileWaves * kWave), shm, s, a);
     return hipGetLastError();
 }
 
@@ -709,15 +709,15 @@ hipError_t p2m(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStre
         if (max_grid) return occupancy(pass2_kernel<Acc, RA, RB, MED, false>, shm, max_grid);
         hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, false>), dim3(a.L.total2),
                            dim3(kTileWaves * kWave), shm, s, a);
-        return hipGetLastError();
+    } else {
+        if (max_grid) return occupancy(pass2_kernel<Acc, RA, RB, MED, true>, shm, max_grid);
+        if (grid >= a.L.total2)
+            hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, false>), dim3(a.L.total2),
+                               dim3(kTileWaves * kWave), shm, s, a);
+        else
+            hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, true>), dim3(grid),
+                               dim3(kTileWaves * kWave), shm, s, a);
     }
-    if (max_grid) return occupancy(pass2_kernel<Acc, RA, RB, MED, true>, shm, max_grid);
-    if (grid >= a.L.total2)
-        hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, false>), dim3(a.L.total2),
-                           dim3(kTileWaves * kWave), shm, s, a);
-    else
-        hipLaunchKernelGGL((pass2_kernel<Acc, RA, RB, MED, true>), dim3(grid),
-                           dim3(kTileWaves * kWave), shm, s, a);
     return hipGetLastError();
 }
 template <class Acc, int RA, int RB>

@@ -14,6 +14,8 @@
 
 namespace logfx {
 
+namespace {   // one copy per radius pair: internal linkage keeps the units' copies apart
+
 // Pass-1 variants built: statistics only, maps, cells, stored strengths,
 // stored strengths with cells.
 template <class Acc>
@@ -28,6 +30,8 @@ hipError_t pass1_any(const Pass1Args<typename kern::AccOps<Acc>::Taps> &a, int m
     default: return hipErrorInvalidValue;
     }
 }
+}  // namespace
+
 hipError_t LOGFX_FN(pass1_i)(const Pass1Args<OrbitTapsI> &a, int mode, int grid, hipStream_t s,
                              int *max_grid) {
     return pass1_any<int>(a, mode, grid, s, max_grid);
