@@ -131,13 +131,17 @@ __device__ inline bool opposite(double p, double q) { return p * q < 0.0; }
 // lane of the wave holds a zero.  Written without short-circuit logic so
 // that it compiles to straight-line code.
 template <class Acc, class Thr>
-__device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
+__device__ inline Acc zc_value(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
     const Acc qmax = max(max(up, dn), max(lf, rt));
     const Acc qmin = min(min(up, dn), min(lf, rt));
     bool is = ((a < 0) & (a + qmax >= 0)) | ((a > 0) & (a + qmin < 0));
     if (__ballot(a == 0)) is = is | ((a == 0) & (opposite(lf, rt) | opposite(up, dn)));
     const Acc c = max(a, qmax) - min(a, qmin);   // exact: |L| < 2^30 (int) or 2^52 (FP64)
-    return AccOps<Acc>::to_d((is & (c > thr)) ? c : Acc(0));
+    return (is & (c > thr)) ? c : Acc(0);
+}
+template <class Acc, class Thr>
+__device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
+    return AccOps<Acc>::to_d(zc_value<Acc>(a, up, dn, lf, rt, thr));
 }
 
 __device__ inline double wave_sum(double v) {
@@ -354,9 +358,7 @@ __device__ inline ImageJob job_of(const Launch &L, int image) {
 template <class Acc> struct ZStore;
 template <> struct ZStore<int> {
     using T = int2;
-    __device__ static void put(void *m, long long at, const double (&z)[2]) {
-        static_cast<int2 *>(m)[at] = make_int2((int)z[0], (int)z[1]);
-    }
+    __device__ static T make(const int (&z)[2]) { return make_int2(z[0], z[1]); }
     __device__ static void get(const T &v, double &z0, double &z1) {
         z0 = (double)v.x;
         z1 = (double)v.y;
@@ -364,9 +366,7 @@ template <> struct ZStore<int> {
 };
 template <> struct ZStore<double> {
     using T = double2;
-    __device__ static void put(void *m, long long at, const double (&z)[2]) {
-        static_cast<double2 *>(m)[at] = make_double2(z[0], z[1]);
-    }
+    __device__ static T make(const double (&z)[2]) { return make_double2(z[0], z[1]); }
     __device__ static void get(const T &v, double &z0, double &z1) {
         z0 = v.x;
         z1 = v.y;
@@ -461,19 +461,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
         // zero crossings of row t - 1 (valid from the third step on)
         const int r = t - 1;
         const bool use = g.outc & (si >= 2);
-        double zr[2];
+        Acc zr[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const Acc c = L[j][1];
             Acc lf, rt;
             neighbours<C>(c, g.clampL, g.clampR, lf, rt);
-            const double z = zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j));
+            zr[j] = zc_value<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j));
+            const double z = AccOps<Acc>::to_d(zr[j]);
             const double zu = use ? z : 0.0;
             sz[j] += zu;
             sq[j] = __fma_rn(zu, zu, sq[j]);
             cnt[j] += __popcll(__ballot(zu != 0.0));   // wave-uniform
             if constexpr ((MODE & kP1Cells) != 0) fc += (unsigned)(zu != 0.0) << (16 * j);
-            if constexpr ((MODE & kP1StoreZ) != 0) zr[j] = z;
             if constexpr ((MODE & kP1Maps) != 0) {
                 if (use) {
                     const long long at = (long long)r * g.W + g.xc;
@@ -483,7 +483,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
             }
         }
         if constexpr ((MODE & kP1StoreZ) != 0) {
-            if (use) ZStore<Acc>::put(a.zmap, J.zoff + (long long)r * g.W + g.xc, zr);
+            // the row's base is wave-uniform: scalar base + the lane's column
+            typename ZStore<Acc>::T *zrow =
+                static_cast<typename ZStore<Acc>::T *>(a.zmap) + (J.zoff + (long long)r * g.W);
+            if (use) zrow[g.xc] = ZStore<Acc>::make(zr);
         }
         if constexpr ((MODE & kP1Cells) != 0) {
             fv += use ? (unsigned)h[RB - 1][0] : 0u;   // pixel (r, xc)

@@ -3,7 +3,7 @@
 //
 // Pass 1 has written the pair (Z_1, Z_2) of every pixel to HBM (8 bytes per
 // pixel on the integer path), so this pass computes no LoG: each lane of a
-// wave reads its column's pairs, eight rows ahead, with clamp-to-edge
+// wave reads its column's pairs, six rows ahead, with clamp-to-edge
 // coordinates (the columns and rows outside the image read the edge
 // pixel's pair, which is the clamped operand of the deviation), keeps a
 // ring of three rows of them and the deviation's column sums, takes the row
@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
     using ZT = typename ZStore<Acc>::T;
     __shared__ int redc[2][8];
     constexpr int HL = kHalo2Z, OW = kWave - 2 * HL, TW = tile_out_width(HL);
-    constexpr int G = 8;   // rows read ahead of their use
+    constexpr int G = 6;   // rows read ahead of their use (a multiple of the 3-row ring)
 
     auto tile = [&](const int item, auto medc) __attribute__((always_inline)) {
         constexpr int M = decltype(medc)::value;
@@ -87,7 +87,11 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             orow += opitch;
         };
         auto run = [&](auto clamp) __attribute__((always_inline)) {
-            for (int si0 = 0; si0 < nsteps; si0 += G) {
+            // full groups unrolled (loads first, the ring rotates by
+            // renaming), the rest one step at a time; no step runs under a
+            // condition, which keeps the median's bit rows in scalar registers
+            int si0 = 0;
+            for (; si0 + G <= nsteps; si0 += G) {
                 ZT q[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
@@ -95,8 +99,11 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
                     q[k] = zcol[(long long)row * W];
                 }
 #pragma unroll
-                for (int k = 0; k < G; ++k)
-                    if (si0 + k < nsteps) step(si0 + k, q[k], clamp);
+                for (int k = 0; k < G; ++k) step(si0 + k, q[k], clamp);
+            }
+            for (; si0 < nsteps; ++si0) {
+                const int row = min(max(t0 - 1 + si0, 0), H - 1);
+                step(si0, zcol[(long long)row * W], clamp);
             }
         };
         // the E rows y0-2 .. y0+Rv+1 the output uses lie inside the image:
