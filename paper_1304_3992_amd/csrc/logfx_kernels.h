@@ -376,15 +376,20 @@ template <> struct ZStore<double> {
 // ------------------------------------------------------------- pass 1
 // Occupancy: the integer path is held to 128 VGPRs (4 waves per SIMD, the
 // LDS limit), which costs a few spills but measures faster than 3 waves; the
-// FP64 path keeps its registers.
+// FP64 path keeps its registers.  The variants that store the strengths run
+// at 3 waves without spills: a spill reload waits for every outstanding
+// vector memory operation, the strength stores included (measured 0.33 vs
+// 0.41 ms on the 8192^2 scene).
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
+template <class Acc, int MODE>
+constexpr int kPass1Waves = ((MODE & kP1StoreZ) != 0 && std::is_same<Acc, int>::value) ? 3 : kMinWaves<Acc>;
 
 // MODE, a set of bits: 0 = statistics only; kP1Maps = also the FP64 maps
 // of a single image; kP1Cells = also the per-cell sums of the gate
 // features; kP1StoreZ = also the crossing-strength pair (Z_1, Z_2) of every
 // pixel, for pass 2 to read instead of recomputing it.
 template <class Acc, int RA, int RB, int MODE, bool LOOP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves<Acc, MODE>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ double red[4][8];
     __shared__ long long redc[2][8];
