@@ -51,14 +51,24 @@ PASS2_OPS = {
     "OR, output bit, store": 3,
 }
 PASS2_OPS_PER_PX = sum(PASS2_OPS.values())
+# Pass 1: the same LoG and zero-crossing work as the pass-2 recompute, plus
+# the per-tile sums (convert, add, multiply-add and count per mask).
+PASS1_OPS_PER_PX = 34 + 21 + 2 * 25 + 2 * 4
+# Pass 2 on stored strengths: the deviation (row sums 5, column sums 4,
+# 9Q - S^2 2, compare 1 per mask), OR, output.
+PASS2Z_OPS_PER_PX = 2 * 12 + 3
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy of known size; profiles/pipeline_kernels_8192x8192_u16.md)
 # for the kernel sources with this hash.  Reported only while the sources are
 # unchanged.
-TRAFFIC_SOURCE_HASH = "218dd534cfcad669"
-TRAFFIC_BYTES = {"pass1_kernel": (89861 * 2.0 + 70749 * 1.0) * 1024,
-                 "pass2_kernel": (75349 * 2.0 + 108822 * 1.0) * 1024}
+TRAFFIC_SOURCE_HASH = "8805778511002226"
+TRAFFIC_BYTES = {"pass1_kernel": (69357 * 2.0 + 524953 * 1.0) * 1024,
+                 "pass2z_kernel": (313334 * 2.0 + 96172 * 1.0) * 1024}
+# Algorithmic HBM bytes per pixel of each kernel: pass 1 reads the 16-bit
+# image and writes the (Z_1, Z_2) int32 pair; pass 2 reads the pair and
+# writes the output byte.
+KERNEL_BYTES_PER_PX = {"pass1_kernel": 2 + 8, "pass2z_kernel": 8 + 1}
 
 
 def kernel_source_hash() -> str:
@@ -279,19 +289,25 @@ def main():
         f"fin={avg[1]:.4f} p2={avg[2]:.4f}")
 
     dom = int(np.argmax([avg[0], avg[2]])) * 2  # 0 = pass 1, 2 = pass 2
-    dom_name = "pass2_kernel" if dom == 2 else "pass1_kernel"
+    stored = ctx.get_option(logfx.OPT_STORE_Z) == 1
     if dom == 2:
-        ops_px = PASS2_OPS_PER_PX
-    else:  # pass 1: LoG, zero crossings, sums
-        ops_px = 34 + 21 + 2 * 25 + 2 * 4
+        dom_name = "pass2z_kernel" if stored else "pass2_kernel"
+        ops_px = PASS2Z_OPS_PER_PX if stored else PASS2_OPS_PER_PX
+    else:
+        dom_name = "pass1_kernel"
+        ops_px = PASS1_OPS_PER_PX
     achieved = ops_px * px / (avg[dom] * 1e-3) / 1e12
     roofline = {
         "bound": "alu", "kernel": dom_name,
         "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
         "frac": round(achieved / VALU_PEAK_TOPS, 4),
         "traffic": (TRAFFIC_BYTES[dom_name] if kernel_source_hash() == TRAFFIC_SOURCE_HASH
-                    and H == 8192 and W == 8192 else None),
+                    and dom_name in TRAFFIC_BYTES and H == 8192 and W == 8192 else None),
         "ops_per_pixel": ops_px,
+        "kernel_hbm": ({"bytes_per_pixel": KERNEL_BYTES_PER_PX[dom_name],
+                        "achieved_GBs": round(KERNEL_BYTES_PER_PX[dom_name] * px / (avg[dom] * 1e-3) / 1e9, 1),
+                        "frac": round(KERNEL_BYTES_PER_PX[dom_name] * px / (avg[dom] * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS, 4)} if dom_name in KERNEL_BYTES_PER_PX else None),
         "hbm_view": {"bytes_per_pixel": 3, "achieved_GBs": round(3 * px / (ms_step * 1e-3) / 1e9, 1),
                      "peak_GBs": HBM_PEAK_GBS,
                      "frac": round(3 * px / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

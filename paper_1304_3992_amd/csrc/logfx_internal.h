@@ -27,7 +27,8 @@ constexpr int kP1StoreZ = 4;   // the (Z_1, Z_2) pair of every pixel for pass 2
 
 // Side of the cell grid over which pass 1 sums the smoothing gate's
 // features (kGateCells x kGateCells cells per image).
-constexpr int kGateCells = 128;
+constexpr int kGateCellsLog2 = 7;
+constexpr int kGateCells = 1 << kGateCellsLog2;
 
 // Orbit index of the D4 orbit {(+-i, +-j), (+-j, +-i)}, 0 <= j <= i.
 __host__ __device__ constexpr int orbit_index(int i, int j) { return i * (i + 1) / 2 + j; }

@@ -203,6 +203,29 @@ __device__ inline uint64_t hmed3(const uint64_t (&e)[5]) {
     const uint64_t x = maj5(sh<-1>(e[1]), sh<1>(e[1]), e[2], sh<-1>(e[3]), sh<1>(e[3]));
     return maj3(p, x, e[2]);
 }
+// Hybrid median of the rows e[0..4] around row 2 (M = 3 or 5); a wave row
+// whose window holds no extracted pixel stays 0 without the bit network.
+template <int M>
+__device__ inline uint64_t hybrid_median(const uint64_t (&e)[5]) {
+    if ((e[0] | e[1] | e[2] | e[3] | e[4]) == 0) return 0;
+    if constexpr (M == 3) return hmed3(e);
+    else return hmed5(e);
+}
+
+// Row sums of the 3x3 deviation (eq. (2)) at one pixel: s = z_l + z + z_r
+// and q = z_l^2 + z^2 + z_r^2 of the pixel's row, in a fixed FP64 order
+// that every pass uses, so that the deviation test decides the same way.
+__device__ inline void dev_row(double zl, double z, double zr, double &s, double &q) {
+    s = (zl + z) + zr;
+    q = __fma_rn(zr, zr, __fma_rn(zl, zl, z * z));
+}
+// 72 s^2 = 9 sum z^2 - (sum z)^2 over the three rows of the window.
+__device__ inline double dev_72var(const double (&s)[3], const double (&q)[3]) {
+    const double S = (s[0] + s[1]) + s[2];
+    const double Q = (q[0] + q[1]) + q[2];
+    return __fma_rn(-S, S, 9.0 * Q);
+}
+
 // Replicate the bit of the first / last in-image lane into the lanes that
 // lie left / right of the image, so shifted reads see clamped columns.
 __device__ inline uint64_t clamp_bits(uint64_t e, int lo, int hi) {
@@ -352,6 +375,10 @@ __device__ inline ImageJob job_of(const Launch &L, int image) {
     return L.nimg == 1 ? L.one : L.jobs[image];
 }
 
+// 1 if a crossing strength (never negative) is non-zero, else 0.
+__device__ inline unsigned nonzero(int z) { return min((unsigned)z, 1u); }
+__device__ inline unsigned nonzero(double z) { return z != 0.0 ? 1u : 0u; }
+
 // Storage of the crossing-strength pair of a pixel between the passes: the
 // integer path keeps the exact integer strengths as int32 pairs, the FP64
 // path as double pairs (LoG grid units either way).
@@ -422,15 +449,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     long long fnext = 0;        // first row of the next cell row
     unsigned long long *fcells = nullptr;
     if constexpr ((MODE & kP1Cells) != 0) {
-        fkey = g.outc ? (int)(((long long)g.xc * kGateCells) / g.W) : (g.lane < HL ? -1 : kGateCells);
-        fcy = (int)(((long long)g.y0 * kGateCells) / g.H);
-        fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) / kGateCells;
+        // floor(n * cells / d) in FP64: exact, since n * cells < 2^53 and a
+        // non-integer quotient lies at least 1/d from an integer
+        fkey = g.outc ? (int)floor((double)g.xc * kGateCells / (double)g.W) : (g.lane < HL ? -1 : kGateCells);
+        fcy = (int)floor((double)g.y0 * kGateCells / (double)g.H);
+        fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2;
         fcells = a.cells + (long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) * 2 * kGateCells * kGateCells;
     }
+    // lanes per cell: at most ceil(W / cells); the scan needs log2 of that steps
+    const int fspan = min(kWave, (g.W + kGateCells - 1) / kGateCells);
     auto flush = [&](const int r) __attribute__((always_inline)) {
-        unsigned v = fv, c = fc;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {   // segmented inclusive scan over equal keys
+        unsigned v = g.outc ? fv : 0u, c = g.outc ? fc : 0u;
+        for (int off = 1; off < fspan; off <<= 1) {   // segmented inclusive scan over equal keys
             const unsigned v2 = __shfl_up(v, off), c2 = __shfl_up(c, off);
             const int k2 = __shfl_up(fkey, off);
             if (g.lane >= off && k2 == fkey) v += v2, c += c2;
@@ -443,8 +473,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
                       (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
         }
         fv = fc = 0;
-        fcy = (int)(((long long)(r + 1) * kGateCells) / g.H);
-        fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) / kGateCells;
+        // the cell row of row r + 1 (cells may be empty when H < cells):
+        // the first c > fcy whose rows reach past r, by shifts only
+        int cy = fcy + 1;
+        while (((((long long)cy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2) <= r + 1) ++cy;
+        fcy = cy;
+        fnext = (((long long)cy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2;
     };
 
     // One step = one new input row.  Full groups of P steps are unrolled so
@@ -478,7 +512,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             sz[j] += zu;
             sq[j] = __fma_rn(zu, zu, sq[j]);
             cnt[j] += __popcll(__ballot(zu != 0.0));   // wave-uniform
-            if constexpr ((MODE & kP1Cells) != 0) fc += (unsigned)(zu != 0.0) << (16 * j);
             if constexpr ((MODE & kP1Maps) != 0) {
                 if (use) {
                     const long long at = (long long)r * g.W + g.xc;
@@ -494,8 +527,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             if (use) zrow[g.xc] = ZStore<Acc>::make(zr);
         }
         if constexpr ((MODE & kP1Cells) != 0) {
-            fv += use ? (unsigned)h[RB - 1][0] : 0u;   // pixel (r, xc)
-            if (si >= 2 && (r + 1 == fnext || r == g.y0 + g.Rv - 1)) flush(r);
+            // every lane accumulates; the halo rows before the strip are
+            // dropped below and the non-output lanes at the flush
+            fv += (unsigned)h[RB - 1][0];   // pixel (r, xc)
+            fc += nonzero(zr[0]) + (nonzero(zr[1]) << 16);
+            if (si < 2) fv = fc = 0;
+            else if (r + 1 == fnext || r == g.y0 + g.Rv - 1) flush(r);
         }
     };
     auto run = [&](auto clamp) __attribute__((always_inline)) {
@@ -572,7 +609,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
 #pragma unroll
     for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * g.stride + g.lc, h[s + 1]);
     Acc L[2][3] = {{0, 0, 0}, {0, 0, 0}};        // rows t-2, t-1, t
-    double Z[2][3] = {{0, 0, 0}, {0, 0, 0}};     // rows t-3, t-2, t-1
+    double Zs[2][3] = {{0, 0, 0}, {0, 0, 0}};    // deviation row sums, rows t-3, t-2, t-1
+    double Zq[2][3] = {{0, 0, 0}, {0, 0, 0}};
     uint64_t e[5] = {0, 0, 0, 0, 0};             // rows t-6 .. t-2
     int ecnt = 0, fcnt = 0;
     const int nsteps = g.Rv + 2 * HL;
@@ -602,33 +640,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<A
         // before their inputs are valid leaves the rings before any output
         // uses it.  Only the output is guarded.
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {   // zero-crossing strength of row t - 1
+        for (int j = 0; j < 2; ++j) {   // zero-crossing strength of row t - 1 and its row sums
             const Acc c = L[j][1];
             Acc lf, rt;
             neighbours<C>(c, g.clampL, g.clampR, lf, rt);
-            ring_push<C>(Z[j], zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j)),
-                         t - 1, g.H);
+            const double z = zc_strength<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j));
+            double zl, zr, hs, hq;
+            neighbours<C>(z, g.clampL, g.clampR, zl, zr);
+            dev_row(zl, z, zr, hs, hq);
+            ring_push<C>(Zs[j], hs, t - 1, g.H);
+            ring_push<C>(Zq[j], hq, t - 1, g.H);
         }
         bool ej = false;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {   // extraction of row t - 2: 3x3 deviation of Z
-            const double cs = Z[j][0] + Z[j][1] + Z[j][2];
-            const double cq = __fma_rn(Z[j][0], Z[j][0], __fma_rn(Z[j][1], Z[j][1], Z[j][2] * Z[j][2]));
-            double csl, csr, cql, cqr;
-            neighbours<C>(cs, g.clampL, g.clampR, csl, csr);
-            neighbours<C>(cq, g.clampL, g.clampR, cql, cqr);
-            const double S = csl + cs + csr;
-            const double Q = cql + cq + cqr;
-            // 9 sum z^2 - (sum z)^2 = 72 s^2 for the unbiased s of eq. (2)
-            const double V = __fma_rn(-S, S, 9.0 * Q);
-            ej = ej || (V > (j == 0 ? thr72_0 : thr72_1));
-        }
+        for (int j = 0; j < 2; ++j)     // extraction of row t - 2: 3x3 deviation of Z
+            ej = ej || (dev_72var(Zs[j], Zq[j]) > (j == 0 ? thr72_0 : thr72_1));
         ring_push<C>(e, clamp_bits(__ballot(ej), lo_lane, hi_lane), t - 2, g.H);
         // output row t - 4 (from the ninth step on)
         uint64_t f;
         if constexpr (M == 0) f = e[2];
-        else if constexpr (M == 3) f = hmed3(e);
-        else f = hmed5(e);
+        else f = hybrid_median<M>(e);
         if (si >= 8) {
             if (g.outc) *orow = (uint8_t)((f & mybit) != 0);
             fcnt += __popcll(f & outmask);       // wave-uniform counts

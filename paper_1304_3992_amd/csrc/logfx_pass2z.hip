@@ -6,8 +6,8 @@
 // wave reads its column's pairs, six rows ahead, with clamp-to-edge
 // coordinates (the columns and rows outside the image read the edge
 // pixel's pair, which is the clamped operand of the deviation), keeps a
-// ring of three rows of them and the deviation's column sums, takes the row
-// sums from the neighbouring lanes, and continues exactly as the pass that
+// ring of three rows of the deviation's row sums (the neighbours from the
+// adjacent lanes), and continues exactly as the pass that
 // recomputes the strengths: same FP64 operations in the same order, so the
 // two passes give the same output bit for bit.  No LDS; halo 3 columns
 // (median 2 + deviation 1), 58 output columns per wave.
@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         const uint64_t mybit = 1ull << lane;
         const uint64_t outmask = __ballot(outc);
 
-        double Z[2][3] = {{0, 0, 0}, {0, 0, 0}};   // rows t-3, t-2, t-1
+        double Zs[2][3] = {{0, 0, 0}, {0, 0, 0}};  // deviation row sums, rows t-3, t-2, t-1
+        double Zq[2][3] = {{0, 0, 0}, {0, 0, 0}};
         uint64_t e[5] = {0, 0, 0, 0, 0};           // rows t-6 .. t-2
         int ecnt = 0, fcnt = 0;
         // step si reads Z row t - 1 = y0 - 3 + si; rows y0-3 .. y0+Rv+2
@@ -58,27 +59,24 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             double zn[2];
             ZStore<Acc>::get(zv, zn[0], zn[1]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                Z[j][0] = Z[j][1];
-                Z[j][1] = Z[j][2];
-                Z[j][2] = zn[j];
+            for (int j = 0; j < 2; ++j) {   // row sums of row t - 1 (columns clamped by the loads)
+                double hs, hq;
+                dev_row(from_left(zn[j]), zn[j], from_right(zn[j]), hs, hq);
+                Zs[j][0] = Zs[j][1];
+                Zs[j][1] = Zs[j][2];
+                Zs[j][2] = hs;
+                Zq[j][0] = Zq[j][1];
+                Zq[j][1] = Zq[j][2];
+                Zq[j][2] = hq;
             }
             bool ej = false;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {   // extraction of row t - 2: 3x3 deviation of Z
-                const double cs = Z[j][0] + Z[j][1] + Z[j][2];
-                const double cq = __fma_rn(Z[j][0], Z[j][0], __fma_rn(Z[j][1], Z[j][1], Z[j][2] * Z[j][2]));
-                const double S = from_left(cs) + cs + from_right(cs);
-                const double Q = from_left(cq) + cq + from_right(cq);
-                // 9 sum z^2 - (sum z)^2 = 72 s^2 for the unbiased s of eq. (2)
-                const double V = __fma_rn(-S, S, 9.0 * Q);
-                ej = ej || (V > (j == 0 ? thr72_0 : thr72_1));
-            }
+            for (int j = 0; j < 2; ++j)     // extraction of row t - 2: 3x3 deviation of Z
+                ej = ej || (dev_72var(Zs[j], Zq[j]) > (j == 0 ? thr72_0 : thr72_1));
             ring_push<C>(e, clamp_bits(__ballot(ej), lo_lane, hi_lane), t - 2, H);
             uint64_t f;   // output row t - 4 (from the seventh step on)
             if constexpr (M == 0) f = e[2];
-            else if constexpr (M == 3) f = hmed3(e);
-            else f = hmed5(e);
+            else f = hybrid_median<M>(e);
             if (si >= 6) {
                 if (outc) *orow = (uint8_t)((f & mybit) != 0);
                 fcnt += __popcll(f & outmask);
