@@ -130,14 +130,15 @@ __device__ inline bool opposite(double p, double q) { return p * q < 0.0; }
 // up/down neighbours have opposite signs; that test only runs when some
 // lane of the wave holds a zero.  Written without short-circuit logic so
 // that it compiles to straight-line code.
+// keep: an extra condition folded into the selection (0 where false).
 template <class Acc, class Thr>
-__device__ inline Acc zc_value(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
+__device__ inline Acc zc_value(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr, bool keep = true) {
     const Acc qmax = max(max(up, dn), max(lf, rt));
     const Acc qmin = min(min(up, dn), min(lf, rt));
     bool is = ((a < 0) & (a + qmax >= 0)) | ((a > 0) & (a + qmin < 0));
     if (__ballot(a == 0)) is = is | ((a == 0) & (opposite(lf, rt) | opposite(up, dn)));
     const Acc c = max(a, qmax) - min(a, qmin);   // exact: |L| < 2^30 (int) or 2^52 (FP64)
-    return (is & (c > thr)) ? c : Acc(0);
+    return (is & (c > thr) & keep) ? c : Acc(0);
 }
 template <class Acc, class Thr>
 __device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
@@ -506,12 +507,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             const Acc c = L[j][1];
             Acc lf, rt;
             neighbours<C>(c, g.clampL, g.clampR, lf, rt);
-            zr[j] = zc_value<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j));
+            // the strength where this lane holds an output pixel of the strip, else 0
+            zr[j] = zc_value<Acc>(c, L[j][0], L[j][2], lf, rt, AccOps<Acc>::thr(a, j), use);
             const double z = AccOps<Acc>::to_d(zr[j]);
-            const double zu = use ? z : 0.0;
-            sz[j] += zu;
-            sq[j] = __fma_rn(zu, zu, sq[j]);
-            cnt[j] += __popcll(__ballot(zu != 0.0));   // wave-uniform
+            sz[j] += z;
+            sq[j] = __fma_rn(z, z, sq[j]);
+            cnt[j] += __popcll(__ballot(zr[j] != Acc(0)));   // wave-uniform
             if constexpr ((MODE & kP1Maps) != 0) {
                 if (use) {
                     const long long at = (long long)r * g.W + g.xc;

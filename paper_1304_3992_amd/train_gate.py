@@ -2,16 +2,17 @@
 and AdamW kernels.
 
     python -m paper_1304_3992_amd.train_gate --labels tests/golden/gate_labels.npz \
-        --out paper_1304_3992_amd/gate_weights.bin
+        tests/golden/gate_labels_2048.npz --out paper_1304_3992_amd/gate_weights.bin
 
 The training tiles are the seeded 11-bit scenes of ``scenes.gate_tile``
-(index i, noisy version); their labels (smooth or not) come from a label
-file: arrays ``label``, ``d_raw``, ``d_med`` (the disagreement with the
-noise-free map without and with the hybrid median) and the tile ``size``
-and ``count``.  The tiles are split in order: the first 80 % train, the
-next 10 % validate (the epoch with the lowest validation loss is kept), the
-last 10 % test.  Features are computed on the GPU by pass 1 (one batch call
-per chunk of tiles) and stay resident in device memory for the whole run.
+(index i, noisy version); their labels (smooth or not) come from label
+files, one per tile size: arrays ``label``, ``d_raw``, ``d_med`` (the
+disagreement with the noise-free map without and with the hybrid median),
+the tile ``size``, ``count`` and the generator's ``base_seed``.  The tiles
+of each file are split in order: the first 80 % train, the next 10 %
+validate (the epoch with the lowest validation loss is kept), the last 10 %
+test.  Features are computed on the GPU by pass 1 (one batch call per chunk
+of tiles) and stay resident in device memory for the whole run.
 """
 from __future__ import annotations
 
@@ -26,16 +27,9 @@ import numpy as np
 
 from . import logfx, scenes
 
-_SIZE = 512
-
-
-def _noisy(i):
-    return scenes.gate_tile(i, _SIZE, twin=False)[0]
-
-
-def _init_worker(size):
-    global _SIZE
-    _SIZE = size
+def _noisy(job):
+    i, size, base_seed = job
+    return scenes.gate_tile(i, size, base_seed, twin=False)[0]
 
 
 def he_uniform(seed: int) -> np.ndarray:
@@ -60,21 +54,31 @@ def default_params():
     return logfx.Params(t1, t2)
 
 
-def compute_features(ctx, pool, count, chunk=256, log=print):
-    """bfloat16 features [count, 3, 128, 128] of the noisy tiles, on the GPU.
-    pool: worker processes that generate the tiles (started before the
-    process touched the GPU)."""
+def compute_features(ctx, pool, jobs, log=print):
+    """bfloat16 features [len(jobs), 3, 128, 128] of the noisy tiles
+    (jobs: (index, size, base_seed) each), on the GPU.  pool: worker
+    processes that generate the tiles (started before the process touched
+    the GPU)."""
     import torch
-    feats = torch.empty((count, 3, logfx.GATE_CELLS, logfx.GATE_CELLS), dtype=torch.bfloat16, device="cuda")
+    n = len(jobs)
+    feats = torch.empty((n, 3, logfx.GATE_CELLS, logfx.GATE_CELLS), dtype=torch.bfloat16, device="cuda")
     params = default_params()
     t0 = time.time()
-    for c0 in range(0, count, chunk):
-        c1 = min(count, c0 + chunk)
-        tiles = pool.map(_noisy, range(c0, c1))
+    c0 = 0
+    while c0 < n:
+        # about 256 Mpixel per chunk
+        c1 = c0 + 1
+        px = jobs[c0][1] ** 2
+        while c1 < n and px + jobs[c1][1] ** 2 <= (1 << 28):
+            px += jobs[c1][1] ** 2
+            c1 += 1
+        tiles = pool.map(_noisy, jobs[c0:c1])
         devs = [torch.from_numpy(t.view(np.int16)).cuda() for t in tiles]
         ctx.gate_features(devs, params, feats[c0:c1], bits=11)
         torch.cuda.synchronize()
-        log(f"features {c1}/{count} ({time.time() - t0:.0f} s)")
+        del devs
+        log(f"features {c1}/{n} ({time.time() - t0:.0f} s)")
+        c0 = c1
     return feats
 
 
@@ -103,9 +107,9 @@ def gain_report(z, lab, d_raw, d_med):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--labels", required=True)
+    ap.add_argument("--labels", required=True, nargs="+", help="label files (one per tile size)")
     ap.add_argument("--out", required=True)
-    ap.add_argument("--count", type=int, default=0, help="tiles to use (0 = all of the label file)")
+    ap.add_argument("--count", type=int, default=0, help="tiles to use per file (0 = all)")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=3e-3)
@@ -113,25 +117,35 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--report", default="")
     a = ap.parse_args(argv)
-    d = np.load(a.labels)
-    size = int(d["size"])
     # the tile generators are forked before anything initialises the GPU
-    pool = mp.get_context("fork").Pool(min(a.workers, 16), initializer=_init_worker, initargs=(size,))
+    pool = mp.get_context("fork").Pool(min(a.workers, 16))
     import torch
     if not torch.cuda.is_available():
         sys.exit("training runs on the GPU")
-    count = a.count or int(d["count"])
-    lab = d["label"][:count].astype(np.float32)
-    d_raw = d["d_raw"][:count].astype(np.float64)
-    d_med = d["d_med"][:count].astype(np.float64)
-    n_tr, n_va = int(0.8 * count), int(0.1 * count)
-    tr = np.arange(n_tr)
-    va = np.arange(n_tr, n_tr + n_va)
-    te = np.arange(n_tr + n_va, count)
+    jobs, labs, raws, meds, splits = [], [], [], [], []
+    for path in a.labels:
+        d = np.load(path)
+        size = int(d["size"])
+        seed = int(d["base_seed"]) if "base_seed" in d else 400000
+        count = min(a.count or int(d["count"]), int(d["count"]))
+        o = len(jobs)
+        jobs += [(i, size, seed) for i in range(count)]
+        labs.append(d["label"][:count].astype(np.float32))
+        raws.append(d["d_raw"][:count].astype(np.float64))
+        meds.append(d["d_med"][:count].astype(np.float64))
+        n_tr, n_va = int(0.8 * count), int(0.1 * count)
+        splits.append((size, o + np.arange(n_tr), o + np.arange(n_tr, n_tr + n_va), o + np.arange(n_tr + n_va, count)))
+    lab, d_raw, d_med = np.concatenate(labs), np.concatenate(raws), np.concatenate(meds)
+    # every tile size weighs the same in an epoch: smaller training sets are
+    # repeated up to the size of the largest
+    n_max = max(len(sp[1]) for sp in splits)
+    tr = np.concatenate([np.resize(sp[1], n_max) for sp in splits])
+    va = np.concatenate([sp[2] for sp in splits])
+    te = np.concatenate([sp[3] for sp in splits])
     log = lambda m: print(m, flush=True)  # noqa: E731
 
     with pool, logfx.Context(0) as ctx:
-        feats = compute_features(ctx, pool, count, log=log)
+        feats = compute_features(ctx, pool, jobs, log=log)
         labels_t = torch.from_numpy(lab).cuda()
         ctx.gate_set_params(he_uniform(a.seed))
         rng = np.random.default_rng(a.seed)
@@ -160,12 +174,13 @@ def main(argv=None):
                 best = (vl, ctx.gate_get_params(), ep + 1)
         ctx.gate_set_params(best[1])
         ctx.gate_save(a.out)
-        _, zt = evaluate(ctx, feats, labels_t, te, a.batch)
-        _, zv = evaluate(ctx, feats, labels_t, va, a.batch)
-        rep = {"best_epoch": best[2], "val_loss": best[0],
-               "val": gain_report(zv, lab[va], d_raw[va], d_med[va]),
-               "test": gain_report(zt, lab[te], d_raw[te], d_med[te]),
-               "train_seconds": time.time() - t0, "tiles": count, "size": size}
+        rep = {"best_epoch": best[2], "val_loss": best[0], "train_seconds": time.time() - t0,
+               "tiles": len(jobs)}
+        for size, _, sva, ste in splits:
+            _, zt = evaluate(ctx, feats, labels_t, ste, a.batch)
+            _, zv = evaluate(ctx, feats, labels_t, sva, a.batch)
+            rep[f"size{size}"] = {"val": gain_report(zv, lab[sva], d_raw[sva], d_med[sva]),
+                                  "test": gain_report(zt, lab[ste], d_raw[ste], d_med[ste])}
         log(json.dumps(rep))
         if a.report:
             with open(a.report, "w") as f:
