@@ -403,30 +403,39 @@ template <> struct ZStore<double> {
 
 // ------------------------------------------------------------- pass 1
 // Occupancy: the integer path is held to 128 VGPRs (4 waves per SIMD, the
-// LDS limit), which costs a few spills but measures faster than 3 waves; the
-// FP64 path keeps its registers.  The variants that store the strengths run
-// at 3 waves without spills: a spill reload waits for every outstanding
-// vector memory operation, the strength stores included (measured 0.33 vs
-// 0.41 ms on the 8192^2 scene).
+// LDS limit); the FP64 path keeps its registers.  The variants that sum the
+// gate's cells, and the persistent variant that stores the strengths, need
+// more and run at 3 waves without spills: a spill reload waits for every
+// outstanding vector memory operation, the strength stores included, and
+// measured slower than the lower occupancy.
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
-template <class Acc, int MODE>
-constexpr int kPass1Waves = ((MODE & kP1StoreZ) != 0 && std::is_same<Acc, int>::value) ? 3 : kMinWaves<Acc>;
+template <class Acc, int MODE, bool LOOP>
+constexpr int kPass1Waves =
+    (std::is_same<Acc, int>::value && ((MODE & kP1Cells) != 0 || ((MODE & kP1StoreZ) != 0 && LOOP))) ? 3
+                                                                                                   : kMinWaves<Acc>;
 
 // MODE, a set of bits: 0 = statistics only; kP1Maps = also the FP64 maps
 // of a single image; kP1Cells = also the per-cell sums of the gate
 // features; kP1StoreZ = also the crossing-strength pair (Z_1, Z_2) of every
 // pixel, for pass 2 to read instead of recomputing it.
 template <class Acc, int RA, int RB, int MODE, bool LOOP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves<Acc, MODE>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves<Acc, MODE, LOOP>))) void pass1_kernel(Pass1Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ double red[4][8];
     __shared__ long long redc[2][8];
+    // cell sums of the current cell row, one slot per cell column the tile
+    // touches (at most its 248 output columns)
+    __shared__ unsigned cellv[(MODE & kP1Cells) != 0 ? tile_out_width(kHalo1) : 1];
+    __shared__ unsigned cellc[(MODE & kP1Cells) != 0 ? tile_out_width(kHalo1) : 1];
     constexpr int HL = kHalo1, P = 2 * RB + 1;
 
     for_each_tile<LOOP>(a.L.total1, [&](const int item) __attribute__((always_inline)) {
     const ImageJob J = job_of(a.L, a.L.nimg == 1 ? 0 : a.L.owner1[item]);
     const Strip<HL, RB> g(J.img, item - J.base1, J.tiles_x1, a.rows);
     g.fill(lds, J.img);
+    if constexpr ((MODE & kP1Cells) != 0) {
+        if (threadIdx.x < Strip<HL, RB>::TW) cellv[threadIdx.x] = cellc[threadIdx.x] = 0;
+    }
     __syncthreads();
 
     int h[P][RB + 1];
@@ -442,37 +451,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     // Feature mode: the image is cut into kGateCells x kGateCells cells
     // (row r and column x belong to cell (r * cells / H, x * cells / W)).
     // Each lane sums its pixel values and crossing indicators down its
-    // column while the rows stay in one cell row; at the end of a cell row
-    // (or of the strip) the lanes of each cell are summed across the wave
-    // and one lane per cell adds the sums to the image's cell counters.
+    // column while the rows stay in one cell row.  At the end of a cell row
+    // (or of the strip) -- a row boundary that every wave of the workgroup
+    // reaches at the same step -- the lanes add their sums into the tile's
+    // LDS slot of their cell, and after a barrier one thread per slot adds
+    // the slot to the image's cell counters (integer atomics, exact).
     unsigned fv = 0, fc = 0;    // value sum; crossings of mask 1 + 2^16 * of mask 2
-    int fkey = 0, fcy = 0;      // this lane's cell column; current cell row
+    int fcy = 0;                // current cell row
+    int fkey0 = 0, fslots = 0;  // the tile's first cell column and its number of cell columns
     long long fnext = 0;        // first row of the next cell row
     unsigned long long *fcells = nullptr;
     if constexpr ((MODE & kP1Cells) != 0) {
         // floor(n * cells / d) in FP64: exact, since n * cells < 2^53 and a
         // non-integer quotient lies at least 1/d from an integer
-        fkey = g.outc ? (int)floor((double)g.xc * kGateCells / (double)g.W) : (g.lane < HL ? -1 : kGateCells);
-        fcy = (int)floor((double)g.y0 * kGateCells / (double)g.H);
+        auto cell_of = [](long long n, long long d) { return (int)floor((double)n * kGateCells / (double)d); };
+        fkey0 = cell_of(g.x0, g.W);
+        fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, g.W) - fkey0 + 1;
+        fcy = cell_of(g.y0, g.H);
         fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2;
         fcells = a.cells + (long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) * 2 * kGateCells * kGateCells;
     }
-    // lanes per cell: at most ceil(W / cells); the scan needs log2 of that steps
-    const int fspan = min(kWave, (g.W + kGateCells - 1) / kGateCells);
     auto flush = [&](const int r) __attribute__((always_inline)) {
-        unsigned v = g.outc ? fv : 0u, c = g.outc ? fc : 0u;
-        for (int off = 1; off < fspan; off <<= 1) {   // segmented inclusive scan over equal keys
-            const unsigned v2 = __shfl_up(v, off), c2 = __shfl_up(c, off);
-            const int k2 = __shfl_up(fkey, off);
-            if (g.lane >= off && k2 == fkey) v += v2, c += c2;
+        const int fkey = (int)floor((double)g.xc * kGateCells / (double)g.W);   // the lane's cell column
+        if (g.outc && (fv | fc)) {
+            atomicAdd(&cellv[fkey - fkey0], fv);
+            atomicAdd(&cellc[fkey - fkey0], fc);
         }
-        const int kn = __shfl_down(fkey, 1);
-        if (g.outc && (g.lane == kWave - 1 || kn != fkey) && (v | c)) {
-            unsigned long long *cell = fcells + (long long)fcy * kGateCells + fkey;
-            atomicAdd(cell, (unsigned long long)v);
-            atomicAdd(cell + kGateCells * kGateCells,
-                      (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
+        __syncthreads();
+        if ((int)threadIdx.x < fslots) {
+            const unsigned v = cellv[threadIdx.x], c = cellc[threadIdx.x];
+            if (v | c) {
+                unsigned long long *cell = fcells + (long long)fcy * kGateCells + fkey0 + threadIdx.x;
+                atomicAdd(cell, (unsigned long long)v);
+                atomicAdd(cell + kGateCells * kGateCells,
+                          (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
+                cellv[threadIdx.x] = cellc[threadIdx.x] = 0;
+            }
         }
+        __syncthreads();
         fv = fc = 0;
         // the cell row of row r + 1 (cells may be empty when H < cells):
         // the first c > fcy whose rows reach past r, by shifts only

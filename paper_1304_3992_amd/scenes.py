@@ -147,21 +147,43 @@ def config3(n: int = 64, seed: int = 3, base_seed: int = 3000, lo: int = 256, hi
     return tiles
 
 
-def gate_tile(index: int, size: int = 512, base_seed: int = 400000, twin: bool = True):
+def gate_tile(index: int, size: int = 512, base_seed: int = 400000, twin: bool = True,
+              band: bool = False):
     """One training tile of the smoothing gate and its noise-free twin: the
     8192^2 generator's density of rectangles and polylines on a size^2 11-bit
     tile, Gaussian noise sigma ~ U[0, 20] and salt-and-pepper density
-    ~ U[0, 0.2].  Returns (noisy, clean, sigma, density); clean is None when
-    twin is False."""
+    ~ U[0, 0.2].  With band, the noise-free tile is first mapped to another
+    band as the four-band workload does (round(g * tile + o), clipped, with
+    gain g ~ U[0.6, 1.2] and offset o ~ U[-60, 100]) and the noise is added
+    to that.  Returns (noisy, clean, sigma, density); clean is None when twin
+    is False (and band is False)."""
     rng = np.random.default_rng(base_seed + index)
     sigma = float(rng.uniform(0.0, 20.0))
     density = float(rng.uniform(0.0, 0.2))
     scale = size * size / float(8192 * 8192)
     kw = dict(n_rect=max(1, round(20000 * scale)), n_poly=max(1, round(500 * scale)), bits=11)
     seed = base_seed + 1_000_000 + index
+    if band:
+        gain, offset = float(rng.uniform(0.6, 1.2)), float(rng.uniform(-60.0, 100.0))
+        base = panchromatic(size, size, seed, noise_sigma=0.0, sp_density=0.0, **kw).astype(np.float64)
+        clean = np.clip(np.rint(gain * base + offset), 0, 2047)
+        noisy = _noise(clean, rng, sigma, density, 2047)
+        return noisy, clean.astype(np.uint16), sigma, density
     noisy = panchromatic(size, size, seed, noise_sigma=sigma, sp_density=density, **kw)
     clean = panchromatic(size, size, seed, noise_sigma=0.0, sp_density=0.0, **kw) if twin else None
     return noisy, clean, sigma, density
+
+
+def _noise(clean: np.ndarray, rng: np.random.Generator, sigma: float, density: float, maxv: int) -> np.ndarray:
+    """Gaussian noise (rounded, clipped) then salt-and-pepper impulses on a
+    noise-free float image; returns uint16."""
+    img = clean + rng.normal(0.0, sigma, size=clean.shape) if sigma > 0 else clean.copy()
+    np.rint(img, out=img)
+    np.clip(img, 0, maxv, out=img)
+    u = rng.random(img.shape)
+    img[u < density / 2] = 0
+    img[(u >= density / 2) & (u < density)] = maxv
+    return img.astype(np.uint16)
 
 
 def sha256(a: np.ndarray) -> str:
@@ -192,13 +214,7 @@ def config5_tile(base: np.ndarray, band: int, ty: int, tx: int, tile: int = 2048
     density = float(rng.uniform(0.0, 0.2))
     b = base[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile].astype(np.float64)
     clean = np.clip(np.rint(C5_GAIN[band] * b + C5_OFFSET[band]), 0, maxv)
-    img = clean + rng.normal(0.0, sigma, size=clean.shape) if sigma > 0 else clean.copy()
-    np.rint(img, out=img)
-    np.clip(img, 0, maxv, out=img)
-    u = rng.random(img.shape)
-    img[u < density / 2] = 0
-    img[(u >= density / 2) & (u < density)] = maxv
-    return img.astype(np.uint16), clean.astype(np.uint16), sigma, density
+    return _noise(clean, rng, sigma, density, maxv), clean.astype(np.uint16), sigma, density
 
 
 def config5_index(size: int = 16384, tile: int = 2048, bands: int = 4):
