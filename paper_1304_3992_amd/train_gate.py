@@ -28,8 +28,8 @@ import numpy as np
 from . import logfx, scenes
 
 def _noisy(job):
-    i, size, base_seed = job
-    return scenes.gate_tile(i, size, base_seed, twin=False)[0]
+    i, size, base_seed, band = job
+    return scenes.gate_tile(i, size, base_seed, twin=False, band=band)[0]
 
 
 def he_uniform(seed: int) -> np.ndarray:
@@ -56,7 +56,7 @@ def default_params():
 
 def compute_features(ctx, pool, jobs, log=print):
     """bfloat16 features [len(jobs), 3, 128, 128] of the noisy tiles
-    (jobs: (index, size, base_seed) each), on the GPU.  pool: worker
+    (jobs: (index, size, base_seed, band) each), on the GPU.  pool: worker
     processes that generate the tiles (started before the process touched
     the GPU)."""
     import torch
@@ -127,14 +127,16 @@ def main(argv=None):
         d = np.load(path)
         size = int(d["size"])
         seed = int(d["base_seed"]) if "base_seed" in d else 400000
+        band = bool(int(d["band"])) if "band" in d else False
         count = min(a.count or int(d["count"]), int(d["count"]))
         o = len(jobs)
-        jobs += [(i, size, seed) for i in range(count)]
+        jobs += [(i, size, seed, band) for i in range(count)]
         labs.append(d["label"][:count].astype(np.float32))
         raws.append(d["d_raw"][:count].astype(np.float64))
         meds.append(d["d_med"][:count].astype(np.float64))
         n_tr, n_va = int(0.8 * count), int(0.1 * count)
-        splits.append((size, o + np.arange(n_tr), o + np.arange(n_tr, n_tr + n_va), o + np.arange(n_tr + n_va, count)))
+        name = f"size{size}" + ("b" if band else "")
+        splits.append((name, o + np.arange(n_tr), o + np.arange(n_tr, n_tr + n_va), o + np.arange(n_tr + n_va, count)))
     lab, d_raw, d_med = np.concatenate(labs), np.concatenate(raws), np.concatenate(meds)
     # every tile size weighs the same in an epoch: smaller training sets are
     # repeated up to the size of the largest
@@ -176,10 +178,10 @@ def main(argv=None):
         ctx.gate_save(a.out)
         rep = {"best_epoch": best[2], "val_loss": best[0], "train_seconds": time.time() - t0,
                "tiles": len(jobs)}
-        for size, _, sva, ste in splits:
+        for name, _, sva, ste in splits:
             _, zt = evaluate(ctx, feats, labels_t, ste, a.batch)
             _, zv = evaluate(ctx, feats, labels_t, sva, a.batch)
-            rep[f"size{size}"] = {"val": gain_report(zv, lab[sva], d_raw[sva], d_med[sva]),
+            rep[name] = {"val": gain_report(zv, lab[sva], d_raw[sva], d_med[sva]),
                                   "test": gain_report(zt, lab[ste], d_raw[ste], d_med[ste])}
         log(json.dumps(rep))
         if a.report:
