@@ -181,7 +181,13 @@ int logfx_extract_maps(logfx_ctx *ctx, const logfx_image *img, const logfx_param
  * workgroups that fit on the device walking all tiles; the launches are
  * replayed from a captured hipGraph unless LOGFX_OPT_GRAPH is 0 (the graph
  * is re-captured when the batch geometry or parameters change).  The image table is uploaded from pinned memory on
- * `stream` before the launches. */
+ * `stream` before the launches.
+ * With p->smooth = LOGFX_SMOOTH_GATE (and gate parameters in the context)
+ * pass 1 also sums each image's gate features, the network decides between
+ * pass 1 and pass 2 which images get the hybrid median, and each report's
+ * smoothed / gated / gate_logit give the decision (at most
+ * LOGFX_GATE_MAX_BATCH images per call; every gate cell must hold fewer than
+ * 2^32 pixels). */
 int logfx_extract_batch(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
                         uint8_t *const *outs, logfx_report *reps, void *stream);
 
@@ -224,8 +230,9 @@ int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_p
  * kernel time, refined per kernel).  While enabled, every extract call on
  * the context records HIP events around its kernels on the call's stream.
  * logfx_timing_read waits for the recorded events and returns summed
- * milliseconds in ms_out[0..3]: pass 1, the finalize kernel, pass 2 (direct
- * launches only; a graph replay is timed as a whole) and the whole call;
+ * milliseconds in ms_out[0..3]: pass 1, the finalize kernel (with the
+ * gate's features and network when it decides), pass 2 (direct launches
+ * only; a graph replay is timed as a whole) and the whole call;
  * *calls_out (nullable) receives the number of timed calls.  It starts a new
  * accumulation, as does enabling or disabling. */
 int logfx_timing_enable(logfx_ctx *ctx, int on);

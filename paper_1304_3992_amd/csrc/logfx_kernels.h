@@ -133,11 +133,14 @@ __device__ inline bool opposite(double p, double q) { return p * q < 0.0; }
 // keep: an extra condition folded into the selection (0 where false).
 template <class Acc, class Thr>
 __device__ inline Acc zc_value(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr, bool keep = true) {
-    const Acc qmax = max(max(up, dn), max(lf, rt));
-    const Acc qmin = min(min(up, dn), min(lf, rt));
-    bool is = ((a < 0) & (a + qmax >= 0)) | ((a > 0) & (a + qmin < 0));
+    // hi / lo: largest / smallest of the five values.  For a < 0, a + hi >= 0
+    // holds iff some neighbour reaches -a (a itself cannot), i.e. iff
+    // a + max(neighbours) >= 0; for a > 0 likewise with lo.
+    const Acc hi = max(max(max(up, dn), max(lf, rt)), a);
+    const Acc lo = min(min(min(up, dn), min(lf, rt)), a);
+    bool is = ((a < 0) & (a + hi >= 0)) | ((a > 0) & (a + lo < 0));
     if (__ballot(a == 0)) is = is | ((a == 0) & (opposite(lf, rt) | opposite(up, dn)));
-    const Acc c = max(a, qmax) - min(a, qmin);   // exact: |L| < 2^30 (int) or 2^52 (FP64)
+    const Acc c = hi - lo;   // exact: |L| < 2^30 (int) or 2^52 (FP64)
     return (is & (c > thr) & keep) ? c : Acc(0);
 }
 template <class Acc, class Thr>

@@ -28,8 +28,14 @@ import numpy as np
 from . import logfx, scenes
 
 def _noisy(job):
-    i, size, base_seed, band = job
+    _, i, size, base_seed, band = job
     return scenes.gate_tile(i, size, base_seed, twin=False, band=band)[0]
+
+
+def _scene_tiles(job):
+    seed, size, tile, locs = job
+    base = scenes.config5_base(size, seed)
+    return [scenes.config5_tile(base, b, ty, tx, tile, seed)[0] for b, ty, tx in locs]
 
 
 def he_uniform(seed: int) -> np.ndarray:
@@ -55,8 +61,10 @@ def default_params():
 
 
 def compute_features(ctx, pool, jobs, log=print):
-    """bfloat16 features [len(jobs), 3, 128, 128] of the noisy tiles
-    (jobs: (index, size, base_seed, band) each), on the GPU.  pool: worker
+    """bfloat16 features [len(jobs), 3, 128, 128] of the noisy tiles, on the
+    GPU.  A job is ("tile", index, size, base_seed, band) -- a
+    scenes.gate_tile -- or ("scene", seed, scene_size, tile, band, ty, tx) --
+    a tile of a four-band scene, scenes.config5_tile.  pool: worker
     processes that generate the tiles (started before the process touched
     the GPU)."""
     import torch
@@ -64,20 +72,40 @@ def compute_features(ctx, pool, jobs, log=print):
     feats = torch.empty((n, 3, logfx.GATE_CELLS, logfx.GATE_CELLS), dtype=torch.bfloat16, device="cuda")
     params = default_params()
     t0 = time.time()
-    c0 = 0
-    while c0 < n:
-        # about 256 Mpixel per chunk
-        c1 = c0 + 1
-        px = jobs[c0][1] ** 2
-        while c1 < n and px + jobs[c1][1] ** 2 <= (1 << 28):
-            px += jobs[c1][1] ** 2
-            c1 += 1
-        tiles = pool.map(_noisy, jobs[c0:c1])
+
+    def run(rows, tiles):
         devs = [torch.from_numpy(t.view(np.int16)).cuda() for t in tiles]
-        ctx.gate_features(devs, params, feats[c0:c1], bits=11)
+        out = torch.empty((len(rows), 3, logfx.GATE_CELLS, logfx.GATE_CELLS), dtype=torch.bfloat16, device="cuda")
+        ctx.gate_features(devs, params, out, bits=11)
+        feats[torch.tensor(rows, device="cuda")] = out
         torch.cuda.synchronize()
-        del devs
-        log(f"features {c1}/{n} ({time.time() - t0:.0f} s)")
+
+    # tiles of scenes: one worker per scene builds the scene and cuts its tiles
+    scene_rows = {}
+    for r, j in enumerate(jobs):
+        if j[0] == "scene":
+            scene_rows.setdefault((j[1], j[2], j[3]), []).append(r)
+    keys = list(scene_rows)
+    for k0 in range(0, len(keys), 16):
+        part = keys[k0:k0 + 16]
+        got = pool.map(_scene_tiles, [(seed, size, tile, [jobs[r][4:7] for r in scene_rows[(seed, size, tile)]])
+                                      for seed, size, tile in part])
+        for key, tiles in zip(part, got):
+            rows = scene_rows[key]
+            for c0 in range(0, len(rows), 32):
+                run(rows[c0:c0 + 32], tiles[c0:c0 + 32])
+        log(f"features of {k0 + len(part)}/{len(keys)} scenes ({time.time() - t0:.0f} s)")
+    # single tiles, about 256 Mpixel per chunk
+    rows = [r for r, j in enumerate(jobs) if j[0] == "tile"]
+    c0 = 0
+    while c0 < len(rows):
+        c1 = c0 + 1
+        px = jobs[rows[c0]][2] ** 2
+        while c1 < len(rows) and px + jobs[rows[c1]][2] ** 2 <= (1 << 28):
+            px += jobs[rows[c1]][2] ** 2
+            c1 += 1
+        run(rows[c0:c1], pool.map(_noisy, [jobs[r] for r in rows[c0:c1]]))
+        log(f"features {c1}/{len(rows)} ({time.time() - t0:.0f} s)")
         c0 = c1
     return feats
 
@@ -126,16 +154,21 @@ def main(argv=None):
     for path in a.labels:
         d = np.load(path)
         size = int(d["size"])
-        seed = int(d["base_seed"]) if "base_seed" in d else 400000
-        band = bool(int(d["band"])) if "band" in d else False
         count = min(a.count or int(d["count"]), int(d["count"]))
         o = len(jobs)
-        jobs += [(i, size, seed, band) for i in range(count)]
+        if "scene_seed" in d:   # tiles of four-band scenes
+            band = True
+            jobs += [("scene", int(d["scene_seed"][i]), int(d["scene_size"]), int(d["tile"]), int(d["band"][i]),
+                      int(d["ty"][i]), int(d["tx"][i])) for i in range(count)]
+        else:
+            seed = int(d["base_seed"]) if "base_seed" in d else 400000
+            band = bool(int(d["band"])) if "band" in d else False
+            jobs += [("tile", i, size, seed, band) for i in range(count)]
         labs.append(d["label"][:count].astype(np.float32))
         raws.append(d["d_raw"][:count].astype(np.float64))
         meds.append(d["d_med"][:count].astype(np.float64))
         n_tr, n_va = int(0.8 * count), int(0.1 * count)
-        name = f"size{size}" + ("b" if band else "")
+        name = ("scenes" if "scene_seed" in d else f"size{size}") + ("b" if band and "scene_seed" not in d else "")
         splits.append((name, o + np.arange(n_tr), o + np.arange(n_tr, n_tr + n_va), o + np.arange(n_tr + n_va, count)))
     lab, d_raw, d_med = np.concatenate(labs), np.concatenate(raws), np.concatenate(meds)
     # every tile size weighs the same in an epoch: smaller training sets are
