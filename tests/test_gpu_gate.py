@@ -290,3 +290,34 @@ def test_gate_bias_forces_each_choice_and_fallback(ctx):
         with pytest.raises(logfx.LogfxError) as e:
             fresh.gate(devs, gparams, bits=11)
         assert e.value.code == logfx.EINVAL
+
+
+@pytest.mark.parametrize("median_size", [3, 5])
+def test_gated_batch_same_with_stored_or_recomputed_strengths(ctx, median_size):
+    """The gated batch gives the same bytes and decisions whether pass 2
+    reads the stored strengths or recomputes them, for both median sizes,
+    and each image's output is its single-call output with that decision."""
+    import torch
+    tiles = _gate_tiles()[:5]
+    _, lib_t = masks()
+    theta = og.init(101)
+    theta[og.NPARAM - 1] = 0.0
+    ctx.gate_set_params(theta)
+    params = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, median_size=median_size)
+    devs = [to_device(t) for t in tiles]
+    res = {}
+    for store in (1, 0):
+        ctx.set_option(logfx.OPT_STORE_Z, store)
+        try:
+            outs, reps = ctx.extract_batch(devs, params, bits=11, report=True)
+        finally:
+            ctx.set_option(logfx.OPT_STORE_Z, 1)
+        torch.cuda.synchronize()
+        res[store] = ([o.cpu().numpy() for o in outs], reps)
+    for a, b in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, b)
+    assert res[0][1] == res[1][1]
+    for d, o, r in zip(devs, res[1][0], res[1][1]):
+        single = ctx.extract(d, logfx.Params(*lib_t, smooth=bool(r["smoothed"]), median_size=median_size),
+                             bits=11).cpu().numpy()
+        assert np.array_equal(o, single)
