@@ -36,12 +36,14 @@ __device__ inline long long clampll(long long v, long long lo, long long hi) {
 }
 
 // Values of the lanes to the left (column x - 1) and right (x + 1), by DPP
-// wave shifts on the vector ALU.  Lanes 0 and 63 keep their own value (they
-// are halo lanes whose results are never used).  At the image border the
-// neighbour is clamped to the lane itself when the tile touches a border
-// (EDGE); interior tiles skip the test.
-__device__ inline int from_left(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
-__device__ inline int from_right(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+// wave shifts on the vector ALU.  Lanes 0 and 63 receive 0 (they are halo
+// lanes whose results are never used; no copy of the source is needed).
+// At the image border the neighbour is clamped to the lane itself when the
+// tile touches a border (EDGE); interior tiles skip the test.
+__device__ inline int from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ inline int from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ inline unsigned from_left(unsigned v) { return (unsigned)from_left((int)v); }
+__device__ inline unsigned from_right(unsigned v) { return (unsigned)from_right((int)v); }
 __device__ inline double from_left(double v) {
     return __hiloint2double(from_left(__double2hiint(v)), from_left(__double2loint(v)));
 }
@@ -136,12 +138,25 @@ __device__ inline Acc zc_value(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr, b
     // hi / lo: largest / smallest of the five values.  For a < 0, a + hi >= 0
     // holds iff some neighbour reaches -a (a itself cannot), i.e. iff
     // a + max(neighbours) >= 0; for a > 0 likewise with lo.
-    const Acc hi = max(max(max(up, dn), max(lf, rt)), a);
-    const Acc lo = min(min(min(up, dn), min(lf, rt)), a);
-    bool is = ((a < 0) & (a + hi >= 0)) | ((a > 0) & (a + lo < 0));
-    if (__ballot(a == 0)) is = is | ((a == 0) & (opposite(lf, rt) | opposite(up, dn)));
+    const Acc hi = max(max(max(max(up, dn), lf), rt), a);
+    const Acc lo = min(min(min(min(up, dn), lf), rt), a);
+    bool is;
+    if constexpr (std::is_same<Acc, int>::value) {
+        // b = a + hi for a <= 0, a + lo for a > 0 (exact: |L| < 2^30); a
+        // crossing iff b and a differ in sign bit.  For a = 0, b = hi >= 0.
+        const int b = a + (a <= 0 ? hi : lo);
+        is = (b ^ a) < 0;
+    } else {
+        is = ((a < 0) & (a + hi >= 0)) | ((a > 0) & (a + lo < 0));
+    }
     const Acc c = hi - lo;   // exact: |L| < 2^30 (int) or 2^52 (FP64)
-    return (is & (c > thr) & keep) ? c : Acc(0);
+    const bool strong = (c > thr) & keep;
+    Acc r = (is & strong) ? c : Acc(0);
+    if (__ballot(a == 0)) {
+        const bool z = (a == 0) & (opposite(lf, rt) | opposite(up, dn));
+        r = (z & strong) ? c : r;
+    }
+    return r;
 }
 template <class Acc, class Thr>
 __device__ inline double zc_strength(Acc a, Acc up, Acc dn, Acc lf, Acc rt, Thr thr) {
@@ -159,61 +174,78 @@ __device__ inline int wave_sum(int v) {
     return v;
 }
 
-// ---- bit-sliced majority logic for the binary hybrid median ----
-// Bit l of a row mask is the pixel of lane l; sh(e, d) moves column x + d
-// to bit l.
+// ---- bit-sliced logic for the binary hybrid median ----
+// Every bit of a word is one pixel.  In the wave-row form bit l of a row
+// mask is the pixel of lane l and sh(e, d) moves column x + d to bit l.
 template <int D>
 __device__ inline uint64_t sh(uint64_t e) {
     if constexpr (D >= 0) return e >> D;
     else return e << (-D);
 }
-__device__ inline uint64_t maj3(uint64_t a, uint64_t b, uint64_t c) { return (a & b) | (c & (a | b)); }
-__device__ inline void fadd(uint64_t a, uint64_t b, uint64_t c, uint64_t &s, uint64_t &cy) {
-    const uint64_t t = a ^ b;
+// Full adder: a + b + c = s + 2 cy.
+template <class T>
+__device__ inline void fadd(T a, T b, T c, T &s, T &cy) {
+    const T t = a ^ b;
     s = t ^ c;
-    cy = (a & b) | (c & t);
+    cy = (t & c) | (~t & a);
 }
-// At least 5 of 9.
-__device__ inline uint64_t maj9(uint64_t x1, uint64_t x2, uint64_t x3, uint64_t x4, uint64_t x5,
-                                uint64_t x6, uint64_t x7, uint64_t x8, uint64_t x9) {
-    uint64_t s1, c1, s2, c2, s3, c3, s4, c4;
-    fadd(x1, x2, x3, s1, c1);
-    fadd(x4, x5, x6, s2, c2);
-    fadd(x7, x8, x9, s3, c3);
-    fadd(s1, s2, s3, s4, c4);
-    // count = s4 + 2 * (#ones among c1..c4); >= 5 <=> #c >= 3, or #c == 2 and s4.
-    const uint64_t ge2 = (c1 & c2) | (c3 & c4) | ((c1 | c2) & (c3 | c4));
-    const uint64_t ge3 = (c1 & c2 & (c3 | c4)) | (c3 & c4 & (c1 | c2));
-    return ge3 | (ge2 & s4);
+// [count >= 2] and [count >= 3] of four pixels.
+template <class T>
+__device__ inline void at_least_2_3_of_4(const T (&v)[4], T &g2, T &g3) {
+    T s1, c1;
+    fadd(v[0], v[1], v[2], s1, c1);
+    const T s = s1 ^ v[3], c2 = s1 & v[3];   // count = s + 2 (c1 + c2)
+    g2 = c1 | c2;
+    g3 = (c1 & c2) | (g2 & s);
 }
-// At least 3 of 5.
-__device__ inline uint64_t maj5(uint64_t x1, uint64_t x2, uint64_t x3, uint64_t x4, uint64_t x5) {
-    uint64_t s1, c1, s2, c2;
-    fadd(x1, x2, x3, s1, c1);
-    fadd(x4, x5, s1, s2, c2);
-    return (c1 & c2) | ((c1 | c2) & s2);
+// [count >= 4] and [count >= 5] of eight pixels.
+template <class T>
+__device__ inline void at_least_4_5_of_8(const T (&v)[8], T &g4, T &g5) {
+    T s1, c1, s2, c2, s3, c3;
+    fadd(v[0], v[1], v[2], s1, c1);
+    fadd(v[3], v[4], v[5], s2, c2);
+    fadd(v[6], v[7], s1, s3, c3);
+    const T s = s2 ^ s3, c4 = s2 & s3;       // count = s + 2 (c1 + c2 + c3 + c4)
+    const T a12 = c1 & c2, a34 = c3 & c4, o12 = c1 | c2, o34 = c3 | c4;
+    g4 = a12 | a34 | (o12 & o34);            // at least two carries
+    g5 = (a12 & o34) | (a34 & o12) | (g4 & s);
 }
-// Hybrid median (Sec. 3.4) of rows e[0..4] = rows r-2..r+2: median of the
-// "+" subgroup, of the "x" subgroup (centre in both) and the centre.
-__device__ inline uint64_t hmed5(const uint64_t (&e)[5]) {
-    const uint64_t p = maj9(sh<-2>(e[2]), sh<-1>(e[2]), e[2], sh<1>(e[2]), sh<2>(e[2]), e[0], e[1],
-                            e[3], e[4]);
-    const uint64_t x = maj9(sh<-2>(e[0]), sh<-1>(e[1]), e[2], sh<1>(e[3]), sh<2>(e[4]), sh<2>(e[0]),
-                            sh<1>(e[1]), sh<-1>(e[3]), sh<-2>(e[4]));
-    return maj3(p, x, e[2]);
+// Hybrid median (Sec. 3.4) of an M x M window of binary pixels: c is the
+// centre, p the other 2M - 2 pixels of the "+" subgroup (centre row and
+// column), x those of the "x" subgroup (the diagonals).  With the centre
+// in both subgroups of 2M - 1 pixels, a subgroup's median is 1 iff it
+// holds at least M ones, so the median of {median(+), median(x), c} is:
+// for c = 1, at least M - 1 ones among the others of either subgroup; for
+// c = 0, at least M ones among the others of both.
+template <int M, class T>
+__device__ inline T hybrid_median_bits(T c, const T (&p)[2 * M - 2], const T (&x)[2 * M - 2]) {
+    static_assert(M == 3 || M == 5, "median window 3 or 5");
+    T p1, p0, x1, x0;
+    if constexpr (M == 3) {
+        at_least_2_3_of_4(p, p1, p0);
+        at_least_2_3_of_4(x, x1, x0);
+    } else {
+        at_least_4_5_of_8(p, p1, p0);
+        at_least_4_5_of_8(x, x1, x0);
+    }
+    return (c & (p1 | x1)) | (~c & p0 & x0);
 }
-__device__ inline uint64_t hmed3(const uint64_t (&e)[5]) {
-    const uint64_t p = maj5(sh<-1>(e[2]), e[2], sh<1>(e[2]), e[1], e[3]);
-    const uint64_t x = maj5(sh<-1>(e[1]), sh<1>(e[1]), e[2], sh<-1>(e[3]), sh<1>(e[3]));
-    return maj3(p, x, e[2]);
-}
-// Hybrid median of the rows e[0..4] around row 2 (M = 3 or 5); a wave row
-// whose window holds no extracted pixel stays 0 without the bit network.
+// Hybrid median of the wave rows e[0..4] (rows r-2 .. r+2) around row 2
+// (M = 3 or 5); a wave row whose window holds no extracted pixel stays 0
+// without the bit network.
 template <int M>
 __device__ inline uint64_t hybrid_median(const uint64_t (&e)[5]) {
     if ((e[0] | e[1] | e[2] | e[3] | e[4]) == 0) return 0;
-    if constexpr (M == 3) return hmed3(e);
-    else return hmed5(e);
+    if constexpr (M == 3) {
+        const uint64_t p[4] = {sh<-1>(e[2]), sh<1>(e[2]), e[1], e[3]};
+        const uint64_t x[4] = {sh<-1>(e[1]), sh<1>(e[1]), sh<-1>(e[3]), sh<1>(e[3])};
+        return hybrid_median_bits<3>(e[2], p, x);
+    } else {
+        const uint64_t p[8] = {sh<-2>(e[2]), sh<-1>(e[2]), sh<1>(e[2]), sh<2>(e[2]), e[0], e[1], e[3], e[4]};
+        const uint64_t x[8] = {sh<-2>(e[0]), sh<2>(e[0]), sh<-1>(e[1]), sh<1>(e[1]),
+                               sh<-1>(e[3]), sh<1>(e[3]), sh<-2>(e[4]), sh<2>(e[4])};
+        return hybrid_median_bits<5>(e[2], p, x);
+    }
 }
 
 // Row sums of the 3x3 deviation (eq. (2)) at one pixel: s = z_l + z + z_r

@@ -7,14 +7,24 @@
 // coordinates (the columns and rows outside the image read the edge
 // pixel's pair, which is the clamped operand of the deviation), keeps a
 // ring of three rows of the deviation's row sums (the neighbours from the
-// adjacent lanes), and continues exactly as the pass that
-// recomputes the strengths: same FP64 operations in the same order, so the
-// two passes give the same output bit for bit.  No LDS; halo 3 columns
-// (median 2 + deviation 1), 58 output columns per wave.
+// adjacent lanes), and runs the same FP64 operations in the same order as
+// the pass that recomputes the strengths, so the two passes give the same
+// output bit for bit.  No LDS; halo 3 columns (median 2 + deviation 1), 58
+// output columns per wave.
+//
+// Each lane collects the E bits of its own column in 32-bit words (bit k =
+// row k of the word).  Once 36 rows past a word's start are known, the
+// hybrid median of the word's 32 output rows is taken on whole words: a
+// row offset is a funnel shift of two consecutive words, a column offset a
+// lane shift, and each logic operation treats 32 pixels.
 #include "logfx_kernels.h"
 
 namespace logfx {
 namespace kern {
+
+typedef __attribute__((address_space(1))) uint8_t GlobalU8;
+// Bits s .. s + 31 of the 64-bit word hi:lo.
+__device__ inline unsigned funnel(unsigned hi, unsigned lo, int s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 
 template <class Acc, int MED, bool LOOP>
 __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
@@ -39,27 +49,80 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         const double thr72_0 = a.stats[image].thr72[0], thr72_1 = a.stats[image].thr72[1];
         const int lo_lane = base < 0 ? -base : 0;
         const int hi_lane = min(max(W - 1 - base, 0), kWave - 1);
-        const uint64_t mybit = 1ull << lane;
-        const uint64_t outmask = __ballot(outc);
+        const unsigned outm = outc ? ~0u : 0u;
 
         double Zs[2][3] = {{0, 0, 0}, {0, 0, 0}};  // deviation row sums, rows t-3, t-2, t-1
         double Zq[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        uint64_t e[5] = {0, 0, 0, 0, 0};           // rows t-6 .. t-2
-        int ecnt = 0, fcnt = 0;
-        // step si reads Z row t - 1 = y0 - 3 + si; rows y0-3 .. y0+Rv+2
+        // E bits of the lane's column: bit k of elo (of ehi) is E row
+        // y0 - 2 + wb + k (+ 32); wb is the first output row, relative to
+        // y0, of the next word to emit
+        unsigned elo = 0, ehi = 0;
+        int wb = 0;
+        bool last = false;                // E bit of the previous row
+        unsigned ecnt = 0, fcnt = 0;      // per lane, output pixels only
+        // step si reads Z row y0 - 3 + si and extracts E row y0 - 4 + si
         const int nsteps = Rv + 2 * HL;
-        const int t0 = y0 - 2;
-        uint8_t *orow = J.out + (long long)(t0 - 4) * J.out_pitch + xc;
-        long long opitch;
-        asm("v_mov_b64 %0, %1" : "=v"(opitch) : "s"(J.out_pitch));
 
+        // F of output rows y0 + wb .. y0 + wb + n - 1 (n <= 32, E rows up to
+        // y0 + wb + n + 1 present)
+        auto emit = [&](const int n) __attribute__((always_inline)) {
+            unsigned w0 = elo, w1 = ehi;
+            if (lo_lane > 0) {   // columns left of the image repeat column 0
+                const unsigned s0 = __builtin_amdgcn_readlane(w0, lo_lane);
+                const unsigned s1 = __builtin_amdgcn_readlane(w1, lo_lane);
+                w0 = lane < lo_lane ? s0 : w0;
+                w1 = lane < lo_lane ? s1 : w1;
+            }
+            if (hi_lane < kWave - 1) {   // columns right of the image repeat column W - 1
+                const unsigned s0 = __builtin_amdgcn_readlane(w0, hi_lane);
+                const unsigned s1 = __builtin_amdgcn_readlane(w1, hi_lane);
+                w0 = lane > hi_lane ? s0 : w0;
+                w1 = lane > hi_lane ? s1 : w1;
+            }
+            // bit k of funnel(.., 2 + d): E row y0 + wb + k + d
+            const unsigned c = funnel(w1, w0, 2);
+            unsigned f;
+            if constexpr (M == 0) {
+                f = c;
+            } else {
+                const unsigned l0 = from_left(w0), l1 = from_left(w1);     // column x - 1
+                const unsigned r0 = from_right(w0), r1 = from_right(w1);   // column x + 1
+                if constexpr (M == 3) {
+                    const unsigned p[4] = {funnel(l1, l0, 2), funnel(r1, r0, 2), funnel(w1, w0, 1), funnel(w1, w0, 3)};
+                    const unsigned x[4] = {funnel(l1, l0, 1), funnel(r1, r0, 1), funnel(l1, l0, 3), funnel(r1, r0, 3)};
+                    f = hybrid_median_bits<3>(c, p, x);
+                } else {
+                    const unsigned ll0 = from_left(l0), ll1 = from_left(l1);     // column x - 2
+                    const unsigned rr0 = from_right(r0), rr1 = from_right(r1);   // column x + 2
+                    const unsigned p[8] = {funnel(ll1, ll0, 2), funnel(l1, l0, 2), funnel(r1, r0, 2), funnel(rr1, rr0, 2),
+                                           w0, funnel(w1, w0, 1), funnel(w1, w0, 3), funnel(w1, w0, 4)};
+                    const unsigned x[8] = {ll0, rr0, funnel(l1, l0, 1), funnel(r1, r0, 1),
+                                           funnel(l1, l0, 3), funnel(r1, r0, 3), funnel(ll1, ll0, 4), funnel(rr1, rr0, 4)};
+                    f = hybrid_median_bits<5>(c, p, x);
+                }
+            }
+            const unsigned rm = (n >= 32 ? ~0u : (1u << n) - 1u) & outm;
+            ecnt += __popc(c & rm);
+            fcnt += __popc(f & rm);
+            // a wave-uniform row address plus the lane's column
+            GlobalU8 *orow = (GlobalU8 *)(J.out + (long long)(y0 + wb) * J.out_pitch);
+            if (outc) {
+#pragma unroll 8
+                for (int k = 0; k < n; ++k) {
+                    orow[(unsigned)xc] = (uint8_t)__builtin_amdgcn_ubfe(f, k, 1);
+                    orow += J.out_pitch;
+                }
+            }
+            elo = ehi;
+            ehi = 0;
+            wb += 32;
+        };
         auto step = [&](const int si, const ZT &zv, auto clamp) __attribute__((always_inline)) {
             constexpr bool C = decltype(clamp)::value;
-            const int t = t0 + si;
             double zn[2];
             ZStore<Acc>::get(zv, zn[0], zn[1]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {   // row sums of row t - 1 (columns clamped by the loads)
+            for (int j = 0; j < 2; ++j) {   // row sums of the row just read (columns clamped by the loads)
                 double hs, hq;
                 dev_row(from_left(zn[j]), zn[j], from_right(zn[j]), hs, hq);
                 Zs[j][0] = Zs[j][1];
@@ -71,36 +134,42 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             }
             bool ej = false;
 #pragma unroll
-            for (int j = 0; j < 2; ++j)     // extraction of row t - 2: 3x3 deviation of Z
+            for (int j = 0; j < 2; ++j)     // 3x3 deviation of Z around the middle row of the ring
                 ej = ej || (dev_72var(Zs[j], Zq[j]) > (j == 0 ? thr72_0 : thr72_1));
-            ring_push<C>(e, clamp_bits(__ballot(ej), lo_lane, hi_lane), t - 2, H);
-            uint64_t f;   // output row t - 4 (from the seventh step on)
-            if constexpr (M == 0) f = e[2];
-            else f = hybrid_median<M>(e);
-            if (si >= 6) {
-                if (outc) *orow = (uint8_t)((f & mybit) != 0);
-                fcnt += __popcll(f & outmask);
-                ecnt += __popcll(e[2] & outmask);
+            if (si >= 2) {
+                const int y = y0 - 4 + si;   // the E row
+                if constexpr (C) {           // rows below the image repeat row H - 1
+                    if (y > H - 1) ej = last;
+                    last = ej;
+                }
+                const int p = si - 2 - wb;   // its bit in elo:ehi
+                const unsigned mlo = p < 32 ? 1u << p : 0u, mhi = p >= 32 ? 1u << (p - 32) : 0u;
+                const unsigned em = ej ? ~0u : 0u;
+                elo |= em & mlo;
+                ehi |= em & mhi;
+                if constexpr (C) {           // rows above the image repeat row 0 (y0 = 0, bits 0 .. 2)
+                    if (y == 0) elo = em & 7u;
+                }
             }
-            orow += opitch;
         };
         auto run = [&](auto clamp) __attribute__((always_inline)) {
             // full groups unrolled (loads first, the ring rotates by
-            // renaming), the rest one step at a time; no step runs under a
-            // condition, which keeps the median's bit rows in scalar registers
+            // renaming), the rest one step at a time
             int si0 = 0;
             for (; si0 + G <= nsteps; si0 += G) {
                 ZT q[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
-                    const int row = min(max(t0 - 1 + si0 + k, 0), H - 1);
+                    const int row = min(max(y0 - 3 + si0 + k, 0), H - 1);
                     q[k] = zcol[(long long)row * W];
                 }
 #pragma unroll
                 for (int k = 0; k < G; ++k) step(si0 + k, q[k], clamp);
+                // E bits wb .. wb + 35 present: the word's 32 output rows are final
+                if (si0 + G - 2 - wb >= 36) emit(32);
             }
             for (; si0 < nsteps; ++si0) {
-                const int row = min(max(t0 - 1 + si0, 0), H - 1);
+                const int row = min(max(y0 - 3 + si0, 0), H - 1);
                 step(si0, zcol[(long long)row * W], clamp);
             }
         };
@@ -108,11 +177,13 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         // no row clamping of the extracted bits
         if (y0 - 2 >= 0 && y0 + Rv + 1 <= H - 1) run(bool_c<false>{});
         else run(bool_c<true>{});
+        while (wb < Rv) emit(min(32, Rv - wb));
 
         const int w = threadIdx.x / kWave;
+        const int es = wave_sum((int)ecnt), fs = wave_sum((int)fcnt);
         if (lane == 0) {
-            redc[0][w] = ecnt;
-            redc[1][w] = fcnt;
+            redc[0][w] = es;
+            redc[1][w] = fs;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
