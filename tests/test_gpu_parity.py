@@ -41,6 +41,8 @@ MAP_CASES = [
     ("c1crop_u8", lambda: scenes.config1()[:300, :250], 0, ((5, 0.8), (9, 1.4)), 16),
     ("rand_u8_ragged", lambda: _rand((131, 301), 255, 3, np.uint8), 0, ((5, 0.8), (9, 1.4)), 16),
     ("scene_u11", lambda: _scene_crop(200, 333, 5, 11), 11, ((5, 0.8), (9, 1.4)), 16),
+    ("r1r2_u12", lambda: _rand((90, 260), 4095, 20, np.uint16), 12, ((3, 0.5), (5, 0.8)), 16),
+    ("r2r3_u12", lambda: _rand((75, 140), 4095, 21, np.uint16), 12, ((5, 0.8), (7, 1.0)), 16),
     ("rand_u16_fp64", lambda: _rand((97, 150), 65535, 4, np.uint16), 16, ((5, 0.8), (9, 1.4)), 16),
     ("grid23_fp64", lambda: scenes.config1()[:128, :300], 0, ((5, 0.8), (9, 1.4)), 23),
     ("swapped_sizes", lambda: _rand((70, 90), 255, 6, np.uint8), 0, ((9, 1.4), (3, 0.5)), 16),
