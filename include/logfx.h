@@ -88,8 +88,13 @@ typedef struct {
  *                deviation of mask j's crossing-strength map);
  *                LOGFX_STD_ABS: T_j = std_k.
  *   std_k      : >= 0.
- *   std5_max   : the paper's 5x5 first stage (Sec. 4.1).  Must be < 0 (off)
- *                in this build; >= 0 returns LOGFX_EUNSUPPORTED.
+ *   std5_max   : the paper's 5x5 first stage (Sec. 4.1).  < 0: off.  >= 0
+ *                (LoG response units): a pixel of mask j is extracted only
+ *                if the unbiased deviation of Z_j over its clamped 5 x 5
+ *                window also exceeds std5_max.  Runs on the strengths
+ *                stored by pass 1 whatever LOGFX_OPT_STORE_Z says
+ *                (LOGFX_ENOMEM if their memory cannot be had).  NaN:
+ *                LOGFX_EINVAL.
  *   smooth     : LOGFX_SMOOTH_NEVER, LOGFX_SMOOTH_ALWAYS (hybrid median) or
  *                LOGFX_SMOOTH_GATE (the gate chooses per image).
  *   median_size: 3 or 5 (window of the hybrid median, Sec. 3.4).

@@ -358,6 +358,7 @@ struct Plan {
     int ra = 1, rb = 1;   // kernel radii, ra <= rb
     int path = LOGFX_PATH_INT32;
     double maxpix = 255.0;
+    bool std5 = false;    // the 5x5 first deviation stage is on (std5_max >= 0)
 };
 
 int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Plan &pl) {
@@ -381,9 +382,6 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     if (!(p->std_k >= 0.0) || !std::isfinite(p->std_k))
         return set_err(ctx, LOGFX_EINVAL, "std_k must be finite and >= 0");
     if (std::isnan(p->std5_max)) return set_err(ctx, LOGFX_EINVAL, "std5_max is NaN");
-    if (p->std5_max >= 0.0)
-        return set_err(ctx, LOGFX_EUNSUPPORTED, "the 5x5 first deviation stage (std5_max >= 0) "
-                                                "is not supported in this build");
     if (p->smooth != LOGFX_SMOOTH_NEVER && p->smooth != LOGFX_SMOOTH_ALWAYS && p->smooth != LOGFX_SMOOTH_GATE)
         return set_err(ctx, LOGFX_EINVAL, "unknown smooth mode %d", p->smooth);
     if (p->median_size != 3 && p->median_size != 5)
@@ -409,6 +407,7 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     else pl.order[0] = 1, pl.order[1] = 0;
     pl.ra = std::max(1, std::min(r0, r1));
     pl.rb = std::max(1, std::max(r0, r1));
+    pl.std5 = p->std5_max >= 0.0;
     return LOGFX_OK;
 }
 
@@ -434,7 +433,8 @@ int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, bool stor
     const long long H = img->height, W = img->width;
     if (H >= (1LL << 30) || W >= (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image sides must be below 2^30");
-    const long long tw1 = tile_out_width(kHalo1), tw2 = tile_out_width(storez ? kHalo2Z : kHalo2);
+    const long long tw1 = tile_out_width(kHalo1);
+    const long long tw2 = tile_out_width(storez ? (pl.std5 ? kHalo2Z5 : kHalo2Z) : kHalo2);
     const long long tx1 = (W + tw1 - 1) / tw1, ty1 = (H + c.rows1 - 1) / c.rows1;
     const long long tx2 = (W + tw2 - 1) / tw2, ty2 = (H + c.rows2 - 1) / c.rows2;
     if (tx1 * ty1 > (1LL << 30) || tx2 * ty2 > (1LL << 30))
@@ -499,12 +499,16 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
     int rc = check_all(ctx, &imgs[0], p, c.pl);
     if (rc != LOGFX_OK) return rc;
     // strengths are stored between the passes when the context allows it and
-    // the memory for them can be had
+    // the memory for them can be had; the 5x5 first stage is built on the
+    // stored strengths only, so it always asks for them
     c.storez = false;
-    if (need_out && ctx->store_z) {
+    if (need_out && (ctx->store_z || c.pl.std5)) {
         long long px = 0;
         for (int i = 0; i < n; ++i) px += (long long)imgs[i].height * imgs[i].width;
         c.storez = ensure_zmap(ctx, px, c.pl.path);
+        if (!c.storez && c.pl.std5)
+            return set_err(ctx, LOGFX_ENOMEM, "the 5x5 first deviation stage needs %lld bytes of device "
+                                              "memory for the crossing strengths", px * (c.pl.path == LOGFX_PATH_INT32 ? 8 : 16));
     }
     const int bits0 = imgs[0].bits == 0 ? (imgs[0].dtype == LOGFX_U8 ? 8 : 16) : imgs[0].bits;
     c.n = n;
@@ -645,6 +649,11 @@ void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *con
         a2.zmap = ctx->zmap;
     }
     a2.median_size = p->median_size;
+    a2.std5 = c.pl.std5 && c.storez;
+    for (int slot = 0; slot < 2; ++slot) {
+        const double t = a2.std5 ? p->std5_max / c.pl.mi[c.pl.order[slot]].unit : 0.0;
+        a2.thr600[slot] = 600.0 * t * t;   // s5 > t <=> 25 sum z^2 - (sum z)^2 > 600 t^2 (t >= 0)
+    }
 }
 
 hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int until) {
@@ -928,7 +937,7 @@ std::string tune_key(logfx_ctx *ctx, const Call &c, const logfx_params *p, const
     k << arch << "|" << (c.pl.path == LOGFX_PATH_INT32 ? "int32" : "fp64") << "|r" << c.pl.ra << c.pl.rb
       << "|" << (img0->dtype == LOGFX_U8 ? "u8" : "u16") << "|med"
       << (p->smooth != LOGFX_SMOOTH_NEVER ? p->median_size : 0) << (p->smooth == LOGFX_SMOOTH_GATE ? "g" : "")
-      << "|" << (c.n > 1 ? "batch" : "single");
+      << "|" << (c.n > 1 ? "batch" : "single") << (c.pl.std5 ? "|s5" : "");
     return k.str();
 }
 

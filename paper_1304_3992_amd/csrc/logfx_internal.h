@@ -17,8 +17,10 @@ constexpr int kMaxOrbits = (kMaxRadius + 1) * (kMaxRadius + 2) / 2;
 //  pass 2: median (+-2) <- local std (+-1) <- zero crossing (+-1) = +-4.
 constexpr int kHalo1 = 1;
 constexpr int kHalo2 = 4;
-//  pass 2 on stored strengths: median (+-2) <- local std (+-1) = +-3.
+//  pass 2 on stored strengths: median (+-2) <- local std (+-1) = +-3;
+//  with the 5x5 first deviation stage, median (+-2) <- 5x5 std (+-2) = +-4.
 constexpr int kHalo2Z = 3;
+constexpr int kHalo2Z5 = 4;
 
 // Pass-1 variants (bits of its MODE).
 constexpr int kP1Maps = 1;     // FP64 maps of L and Z (single images, for inspection)
@@ -123,6 +125,8 @@ struct Pass2Args {
     int median_size;        // 3 or 5
     const int *med_flags;   // [nimg] or nullptr: when given, image i is smoothed iff med_flags[i] != 0
     const void *zmap;       // strength pairs written by pass 1 (pass 2 on stored strengths)
+    int std5;               // the 5x5 first stage: E_j also needs s5 > std5_max (stored strengths only)
+    double thr600[2];       // 600 (std5_max / unit_j)^2, compared with 25 sum z^2 - (sum z)^2
 };
 
 struct FinalizeArgs {
@@ -151,7 +155,8 @@ hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, int gr
                           int *max_grid = nullptr);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 // Pass 2 on the strengths stored by pass 1 (no LoG, no LDS): tiles of
-// tile_out_width(kHalo2Z) columns.
+// tile_out_width(kHalo2Z) columns, or tile_out_width(kHalo2Z5) with the 5x5
+// first stage (a.std5).
 hipError_t launch_pass2z_i(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s, int *max_grid = nullptr);
 hipError_t launch_pass2z_d(const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s, int *max_grid = nullptr);
 

@@ -17,6 +17,10 @@
 // hybrid median of the word's 32 output rows is taken on whole words: a
 // row offset is a funnel shift of two consecutive words, a column offset a
 // lane shift, and each logic operation treats 32 pixels.
+//
+// With the 5x5 first stage (Sec. 4.1, std5_max >= 0) a pixel is extracted
+// only if its 5x5 deviation also exceeds std5_max: a ring of five rows of
+// 5-wide row sums beside the 3-wide ones, halo 4 (56 output columns).
 #include "logfx_kernels.h"
 
 namespace logfx {
@@ -26,12 +30,29 @@ typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 // Bits s .. s + 31 of the 64-bit word hi:lo.
 __device__ inline unsigned funnel(unsigned hi, unsigned lo, int s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 
-template <class Acc, int MED, bool LOOP>
+// Row sums of the 5x5 deviation (the 5x5 first stage, Sec. 4.1): the 3x3
+// row sums (s, q) of the pixel plus its neighbours two columns away.
+__device__ inline void dev_row5(double zl2, double zr2, double s, double q, double &s5, double &q5) {
+    s5 = s + (zl2 + zr2);
+    q5 = __fma_rn(zr2, zr2, __fma_rn(zl2, zl2, q));
+}
+// 600 s5^2 = 25 sum z^2 - (sum z)^2 over the five rows of the window.
+__device__ inline double dev_600var(const double (&s)[5], const double (&q)[5]) {
+    const double S = (((s[0] + s[1]) + s[2]) + s[3]) + s[4];
+    const double Q = (((q[0] + q[1]) + q[2]) + q[3]) + q[4];
+    return __fma_rn(-S, S, 25.0 * Q);
+}
+
+// S5: with the 5x5 first stage, E_j(p) also needs the 5x5 deviation of Z_j
+// above std5_max; the halo grows to 4 columns (56 output columns per wave).
+template <class Acc, int MED, bool LOOP, bool S5>
 __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
     using ZT = typename ZStore<Acc>::T;
     __shared__ int redc[2][8];
-    constexpr int HL = kHalo2Z, OW = kWave - 2 * HL, TW = tile_out_width(HL);
-    constexpr int G = 6;   // rows read ahead of their use (a multiple of the 3-row ring)
+    constexpr int HL = S5 ? kHalo2Z5 : kHalo2Z, OW = kWave - 2 * HL, TW = tile_out_width(HL);
+    constexpr int WR = S5 ? 2 : 1;        // half-height of the widest deviation window
+    constexpr int NR = 2 * WR + 1;        // rows of row sums kept
+    constexpr int G = S5 ? 5 : 6;         // rows read ahead of their use (a multiple of the ring)
 
     auto tile = [&](const int item, auto medc) __attribute__((always_inline)) {
         constexpr int M = decltype(medc)::value;
@@ -51,8 +72,9 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         const int hi_lane = min(max(W - 1 - base, 0), kWave - 1);
         const unsigned outm = outc ? ~0u : 0u;
 
-        double Zs[2][3] = {{0, 0, 0}, {0, 0, 0}};  // deviation row sums, rows t-3, t-2, t-1
-        double Zq[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        const double thr600_0 = a.thr600[0], thr600_1 = a.thr600[1];
+        double Zs[2][NR] = {}, Zq[2][NR] = {};   // 3x3 deviation row sums of the last NR rows read
+        double Ws[2][NR] = {}, Wq[2][NR] = {};   // 5x5 deviation row sums (S5)
         // E bits of the lane's column: bit k of elo (of ehi) is E row
         // y0 - 2 + wb + k (+ 32); wb is the first output row, relative to
         // y0, of the next word to emit
@@ -60,7 +82,7 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         int wb = 0;
         bool last = false;                // E bit of the previous row
         unsigned ecnt = 0, fcnt = 0;      // per lane, output pixels only
-        // step si reads Z row y0 - 3 + si and extracts E row y0 - 4 + si
+        // step si reads Z row y0 - HL + si and extracts E row y0 - HL - WR + si
         const int nsteps = Rv + 2 * HL;
 
         // F of output rows y0 + wb .. y0 + wb + n - 1 (n <= 32, E rows up to
@@ -123,26 +145,44 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             ZStore<Acc>::get(zv, zn[0], zn[1]);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {   // row sums of the row just read (columns clamped by the loads)
+                const double zl = from_left(zn[j]), zr = from_right(zn[j]);
                 double hs, hq;
-                dev_row(from_left(zn[j]), zn[j], from_right(zn[j]), hs, hq);
-                Zs[j][0] = Zs[j][1];
-                Zs[j][1] = Zs[j][2];
-                Zs[j][2] = hs;
-                Zq[j][0] = Zq[j][1];
-                Zq[j][1] = Zq[j][2];
-                Zq[j][2] = hq;
+                dev_row(zl, zn[j], zr, hs, hq);
+#pragma unroll
+                for (int k = 0; k < NR - 1; ++k) {
+                    Zs[j][k] = Zs[j][k + 1];
+                    Zq[j][k] = Zq[j][k + 1];
+                }
+                Zs[j][NR - 1] = hs;
+                Zq[j][NR - 1] = hq;
+                if constexpr (S5) {
+                    double ws, wq;
+                    dev_row5(from_left(zl), from_right(zr), hs, hq, ws, wq);
+#pragma unroll
+                    for (int k = 0; k < NR - 1; ++k) {
+                        Ws[j][k] = Ws[j][k + 1];
+                        Wq[j][k] = Wq[j][k + 1];
+                    }
+                    Ws[j][NR - 1] = ws;
+                    Wq[j][NR - 1] = wq;
+                }
             }
             bool ej = false;
 #pragma unroll
-            for (int j = 0; j < 2; ++j)     // 3x3 deviation of Z around the middle row of the ring
-                ej = ej || (dev_72var(Zs[j], Zq[j]) > (j == 0 ? thr72_0 : thr72_1));
-            if (si >= 2) {
-                const int y = y0 - 4 + si;   // the E row
+            for (int j = 0; j < 2; ++j) {   // deviations of Z around the middle row of the ring
+                const double s3[3] = {Zs[j][WR - 1], Zs[j][WR], Zs[j][WR + 1]};
+                const double q3[3] = {Zq[j][WR - 1], Zq[j][WR], Zq[j][WR + 1]};
+                bool e = dev_72var(s3, q3) > (j == 0 ? thr72_0 : thr72_1);
+                if constexpr (S5) e = e && (dev_600var(Ws[j], Wq[j]) > (j == 0 ? thr600_0 : thr600_1));
+                ej = ej || e;
+            }
+            if (si >= 2 * WR) {
+                const int y = y0 - HL - WR + si;   // the E row
                 if constexpr (C) {           // rows below the image repeat row H - 1
                     if (y > H - 1) ej = last;
                     last = ej;
                 }
-                const int p = si - 2 - wb;   // its bit in elo:ehi
+                const int p = si - 2 * WR - wb;   // its bit in elo:ehi
                 const unsigned mlo = p < 32 ? 1u << p : 0u, mhi = p >= 32 ? 1u << (p - 32) : 0u;
                 const unsigned em = ej ? ~0u : 0u;
                 elo |= em & mlo;
@@ -160,16 +200,16 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
                 ZT q[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
-                    const int row = min(max(y0 - 3 + si0 + k, 0), H - 1);
+                    const int row = min(max(y0 - HL + si0 + k, 0), H - 1);
                     q[k] = zcol[(long long)row * W];
                 }
 #pragma unroll
                 for (int k = 0; k < G; ++k) step(si0 + k, q[k], clamp);
                 // E bits wb .. wb + 35 present: the word's 32 output rows are final
-                if (si0 + G - 2 - wb >= 36) emit(32);
+                if (si0 + G - 2 * WR - wb >= 36) emit(32);
             }
             for (; si0 < nsteps; ++si0) {
-                const int row = min(max(y0 - 3 + si0, 0), H - 1);
+                const int row = min(max(y0 - HL + si0, 0), H - 1);
                 step(si0, zcol[(long long)row * W], clamp);
             }
         };
@@ -208,15 +248,19 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
     });
 }
 
+template <class Acc, int MED, bool S5>
+hipError_t p2z5(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
+    constexpr bool CAN_LOOP = MED >= 0;   // gated variants run one tile per workgroup
+    if (max_grid) return occupancy(pass2z_kernel<Acc, MED, CAN_LOOP, S5>, 0, max_grid);
+    if (!CAN_LOOP || grid >= a.L.total2)
+        hipLaunchKernelGGL((pass2z_kernel<Acc, MED, false, S5>), dim3(a.L.total2), dim3(kTileWaves * kWave), 0, s, a);
+    else
+        hipLaunchKernelGGL((pass2z_kernel<Acc, MED, CAN_LOOP, S5>), dim3(grid), dim3(kTileWaves * kWave), 0, s, a);
+    return hipGetLastError();
+}
 template <class Acc, int MED>
 hipError_t p2z(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
-    constexpr bool CAN_LOOP = MED >= 0;   // gated variants run one tile per workgroup
-    if (max_grid) return occupancy(pass2z_kernel<Acc, MED, CAN_LOOP>, 0, max_grid);
-    if (!CAN_LOOP || grid >= a.L.total2)
-        hipLaunchKernelGGL((pass2z_kernel<Acc, MED, false>), dim3(a.L.total2), dim3(kTileWaves * kWave), 0, s, a);
-    else
-        hipLaunchKernelGGL((pass2z_kernel<Acc, MED, CAN_LOOP>), dim3(grid), dim3(kTileWaves * kWave), 0, s, a);
-    return hipGetLastError();
+    return a.std5 ? p2z5<Acc, MED, true>(a, grid, s, max_grid) : p2z5<Acc, MED, false>(a, grid, s, max_grid);
 }
 
 template <class Acc>

@@ -53,12 +53,18 @@ def run_oracle(img, orc_taps, **kw):
     return oracle.extract(img, orc_taps[0], orc_taps[1], want_intermediates=True, **kw)
 
 
-def band(orc) -> np.ndarray:
+def band(orc, std5_max: float = -1.0) -> np.ndarray:
+    """Band pixels: the oracle's 3x3 deviation (and, with the 5x5 first
+    stage, its 5x5 deviation, from the oracle's own local_std of its Z
+    maps) within BAND_REL of the threshold."""
     b = np.zeros(orc["F"].shape, bool)
     for j, S in ((0, orc["S1"]), (1, orc["S2"])):
         T = orc["stats"][2 + j]
         if T > 0:
             b |= np.abs(S - T) <= BAND_REL * T
+        if std5_max >= 0:
+            S5 = oracle.local_std(orc["Z1" if j == 0 else "Z2"], 5)
+            b |= np.abs(S5 - std5_max) <= BAND_REL * max(std5_max, 1e-300)
     return b
 
 
@@ -74,9 +80,9 @@ def dilate(mask: np.ndarray, r: int) -> np.ndarray:
     return out
 
 
-def compare(F_gpu: np.ndarray, orc, *, smooth: bool, median_size: int = 5) -> dict:
+def compare(F_gpu: np.ndarray, orc, *, smooth: bool, median_size: int = 5, std5_max: float = -1.0) -> dict:
     """Checks the band rule and returns counts."""
-    b = band(orc)
+    b = band(orc, std5_max)
     ref = orc["F"]
     mism = F_gpu != ref
     excused = dilate(b, median_size // 2 if smooth else 0)

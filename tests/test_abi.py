@@ -107,7 +107,8 @@ def test_check_params_rejections(lib):
     assert _rc(_img(), _params(median_size=4))[0] == E
     assert _rc(_img(), _params(std_mode=3))[0] == E
     assert _rc(_img(), _params(flags=1))[0] == E
-    assert _rc(_img(), _params(std5_max=2.0))[0] == U
+    assert _rc(_img(), _params(std5_max=float("nan")))[0] == E
+    assert _rc(_img(), _params(std5_max=2.0)) == (logfx.OK, logfx.PATH_INT32)   # the 5x5 first stage
     p = _params()
     p.c.smooth = 5
     assert _rc(_img(), p)[0] == E

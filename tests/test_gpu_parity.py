@@ -206,3 +206,79 @@ def test_stored_and_recomputed_strengths_agree(ctx, name, make, bits, kw):
     b, rb = run_gpu(ctx, img, lib_t, bits=bits, **kw)
     assert np.array_equal(a, b)
     assert ra == rb
+
+
+def _std5_threshold(img, orc_t, q, **kw):
+    """A 5x5-stage threshold at quantile q of the oracle's own 5x5
+    deviations (the larger of the two masks') at the pixels it extracts
+    without the stage, so that the stage removes part of E."""
+    o = run_oracle(img, orc_t, **kw)
+    s5 = np.maximum(oracle.local_std(o["Z1"], 5), oracle.local_std(o["Z2"], 5))
+    vals = np.unique(s5[o["E"] > 0])
+    if vals.size < 2:
+        return 1.0, o
+    # halfway between two neighbouring values: no pixel sits on the threshold
+    k = min(int(q * (vals.size - 1)), vals.size - 2)
+    return float(0.5 * (vals[k] + vals[k + 1])), o
+
+
+STD5_CASES = [
+    ("c1_q50", lambda: scenes.config1(), 0, 0.5, {}),
+    ("c1_q80_med3", lambda: scenes.config1(), 0, 0.8, dict(median_size=3)),
+    ("c1_zero", lambda: scenes.config1(), 0, None, {}),
+    ("ragged_u11_q60", lambda: _scene_crop(257, 449, 13, 11), 11, 0.6, {}),
+    ("ragged_u8_nosmooth", lambda: _scene_crop(700, 333, 12), 0, 0.4, dict(smooth=False)),
+    ("abs_mode", lambda: scenes.config1(), 0, 0.5, dict(std_mode=logfx.STD_ABS, std_k=6.0)),
+    ("tiny_2x2", lambda: _rand((2, 2), 255, 15, np.uint8), 0, 0.5, {}),
+    ("row_1x300", lambda: _rand((1, 300), 255, 16, np.uint8), 0, 0.5, {}),
+    ("col_300x1", lambda: _rand((300, 1), 255, 17, np.uint8), 0, 0.5, {}),
+    ("u16_fp64", lambda: _scene_crop(190, 230, 14, 16), 16, 0.5, {}),
+]
+
+
+@pytest.mark.parametrize("name,make,bits,q,kw", STD5_CASES, ids=[c[0] for c in STD5_CASES])
+def test_first_stage_5x5(ctx, name, make, bits, q, kw):
+    """The paper's 5x5 first deviation stage (Sec. 4.1, read as: E_j also
+    needs the 5x5 deviation of Z_j above std5_max) against the oracle, with
+    the band rule extended to the 5x5 deviations."""
+    img = make()
+    orc_t, lib_t = masks()
+    if q is None:
+        t, o_off = 0.0, run_oracle(img, orc_t, **kw)
+    else:
+        t, o_off = _std5_threshold(img, orc_t, q, **kw)
+    o = run_oracle(img, orc_t, std5_max=t, **kw)
+    F, rep = run_gpu(ctx, img, lib_t, bits=bits, std5_max=t, **kw)
+    info = compare(F, o, smooth=kw.get("smooth", True), median_size=kw.get("median_size", 5), std5_max=t)
+    assert rep["output"] == int(F.sum())
+    assert abs(rep["extracted"] - int(o["E"].sum())) <= info["band"]
+    # the stage only removes pixels from E
+    assert not (o["E"] & ~o_off["E"]).any()
+    if q is not None and q >= 0.5 and img.size > 10000:
+        assert o["E"].sum() < o_off["E"].sum()
+
+
+def test_first_stage_5x5_batch_and_recompute_setting(ctx):
+    """With the 5x5 stage a batch gives each tile its single-call output, and
+    the stage runs on stored strengths even when the context is set to
+    recompute them."""
+    import torch
+    tiles = scenes.config3(n=5, seed=77, base_seed=7700, lo=60, hi=700)
+    orc_t, lib_t = masks()
+    t, _ = _std5_threshold(tiles[0], orc_t, 0.5)
+    params = logfx.Params(*lib_t, std5_max=t)
+    devs = [to_device(x) for x in tiles]
+    outs = [torch.empty(x.shape, dtype=torch.uint8, device="cuda") for x in tiles]
+    ctx.extract_batch(devs, params, outs, bits=8)
+    singles = []
+    ctx.set_option(logfx.OPT_STORE_Z, 0)
+    try:
+        for d in devs:
+            singles.append(ctx.extract(d, params, bits=8))
+    finally:
+        ctx.set_option(logfx.OPT_STORE_Z, 1)
+    torch.cuda.synchronize()
+    for i, (b, s) in enumerate(zip(outs, singles)):
+        assert torch.equal(b, s), i
+        o = run_oracle(tiles[i], orc_t, std5_max=t)
+        compare(s.cpu().numpy(), o, smooth=True, std5_max=t)
