@@ -27,12 +27,30 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     const ImageJob J = job_of(a.L, image);
     double s[4] = {0, 0, 0, 0};
     long long c[2] = {0, 0};
-    for (int i = t; i < J.ntiles1; i += 256) {
-        const long long at = (long long)J.base1 + i;
+    // thread t adds tiles t, t + 256, ... in that order; U tiles' loads are
+    // in flight at once (a tile past the end adds zeros, which leaves the
+    // sums unchanged)
+    constexpr int U = 8;
+    for (int i0 = t; i0 < J.ntiles1; i0 += 256 * U) {
+        double v[U][4];
+        long long w[U][2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] += a.partials[at * 4 + k];
-        c[0] += a.counts[at * 2];
-        c[1] += a.counts[at * 2 + 1];
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + 256 * u;
+            const long long at = (long long)J.base1 + i;
+            const bool in = i < J.ntiles1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[u][k] = in ? a.partials[at * 4 + k] : 0.0;
+            w[u][0] = in ? a.counts[at * 2] : 0;
+            w[u][1] = in ? a.counts[at * 2 + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[k] += v[u][k];
+            c[0] += w[u][0];
+            c[1] += w[u][1];
+        }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) sd[k][t] = s[k];

@@ -447,6 +447,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     unsigned fv = 0, fc = 0;    // value sum; crossings of mask 1 + 2^16 * of mask 2
     int fcy = 0;                // current cell row
     int fkey0 = 0, fslots = 0;  // the tile's first cell column and its number of cell columns
+    int fslot = 0;              // the LDS slot of the lane's cell column (output lanes)
     long long fnext = 0;        // first row of the next cell row
     unsigned long long *fcells = nullptr;
     if constexpr ((MODE & kP1Cells) != 0) {
@@ -455,15 +456,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         auto cell_of = [](long long n, long long d) { return (int)floor((double)n * kGateCells / (double)d); };
         fkey0 = cell_of(g.x0, g.W);
         fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, g.W) - fkey0 + 1;
+        fslot = g.outc ? cell_of(g.xc, g.W) - fkey0 : 0;
         fcy = cell_of(g.y0, g.H);
         fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2;
         fcells = a.cells + (long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) * 2 * kGateCells * kGateCells;
     }
     auto flush = [&](const int r) __attribute__((always_inline)) {
-        const int fkey = (int)floor((double)g.xc * kGateCells / (double)g.W);   // the lane's cell column
         if (g.outc && (fv | fc)) {
-            atomicAdd(&cellv[fkey - fkey0], fv);
-            atomicAdd(&cellc[fkey - fkey0], fc);
+            atomicAdd(&cellv[fslot], fv);
+            atomicAdd(&cellc[fslot], fc);
         }
         __syncthreads();
         if ((int)threadIdx.x < fslots) {
