@@ -98,7 +98,17 @@ typedef struct {
  *   smooth     : LOGFX_SMOOTH_NEVER, LOGFX_SMOOTH_ALWAYS (hybrid median) or
  *                LOGFX_SMOOTH_GATE (the gate chooses per image).
  *   median_size: 3 or 5 (window of the hybrid median, Sec. 3.4).
- *   flags      : reserved, must be 0. */
+ *   flags      : reserved, must be 0.
+ *   median_cascade: further levels of the hybrid median (Sec. 3.4: the
+ *                filter may be applied repeatedly; Sec. 4.2: the map passes
+ *                through levels of larger and smaller windows).  Entry i,
+ *                3 or 5, is the window of level i + 2, applied to the
+ *                output of level i + 1; a 0 ends the list (all 0: one
+ *                level).  The levels apply wherever the first one does
+ *                (LOGFX_SMOOTH_ALWAYS, or LOGFX_SMOOTH_GATE on the images
+ *                the gate smooths).  Calls with further levels store the
+ *                strengths between the passes whatever LOGFX_OPT_STORE_Z
+ *                says and keep a 1-byte-per-pixel map in the context. */
 typedef struct {
     logfx_mask mask[2];
     double zc_thresh;
@@ -108,6 +118,7 @@ typedef struct {
     int32_t smooth;
     int32_t median_size;
     uint32_t flags;
+    int32_t median_cascade[3];
 } logfx_params;
 
 /* Filled when a call is given a report (the call then waits for its

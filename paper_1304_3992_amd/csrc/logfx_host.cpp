@@ -56,6 +56,8 @@ struct logfx_ctx {
     bool store_z = true;             // pass 1 stores the strengths, pass 2 reads them
     void *zmap = nullptr;            // strength pairs of the images of a call
     long long zcap = 0;              // bytes
+    uint8_t *cmap = nullptr;         // 0/1 maps between the levels of a median cascade
+    long long ccap = 0;              // bytes
     // device scratch
     double *partials = nullptr;      // [cap1][4]
     long long *counts1 = nullptr;    // [cap1][2]
@@ -359,6 +361,8 @@ struct Plan {
     int path = LOGFX_PATH_INT32;
     double maxpix = 255.0;
     bool std5 = false;    // the 5x5 first deviation stage is on (std5_max >= 0)
+    int ncas = 0;         // further median levels (applied where the first level is)
+    int cas[3] = {0, 0, 0};
 };
 
 int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Plan &pl) {
@@ -387,6 +391,13 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     if (p->median_size != 3 && p->median_size != 5)
         return set_err(ctx, LOGFX_EINVAL, "median_size %d is not 3 or 5", p->median_size);
     if (p->flags != 0) return set_err(ctx, LOGFX_EINVAL, "flags must be 0");
+    for (int i = 0; i < 3; ++i) {
+        const int m = p->median_cascade[i];
+        if (m != 0 && m != 3 && m != 5)
+            return set_err(ctx, LOGFX_EINVAL, "median_cascade[%d] = %d is not 0, 3 or 5", i, m);
+        if (m != 0 && i > 0 && p->median_cascade[i - 1] == 0)
+            return set_err(ctx, LOGFX_EINVAL, "median_cascade[%d] follows a 0", i);
+    }
     int rc;
     for (int j = 0; j < 2; ++j)
         if ((rc = analyze_mask(ctx, p->mask[j], j, pl.mi[j])) != LOGFX_OK) return rc;
@@ -408,6 +419,12 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     pl.ra = std::max(1, std::min(r0, r1));
     pl.rb = std::max(1, std::max(r0, r1));
     pl.std5 = p->std5_max >= 0.0;
+    pl.ncas = 0;
+    if (p->smooth != LOGFX_SMOOTH_NEVER)
+        while (pl.ncas < 3 && p->median_cascade[pl.ncas] != 0) {
+            pl.cas[pl.ncas] = p->median_cascade[pl.ncas];
+            ++pl.ncas;
+        }
     return LOGFX_OK;
 }
 
@@ -499,16 +516,30 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
     int rc = check_all(ctx, &imgs[0], p, c.pl);
     if (rc != LOGFX_OK) return rc;
     // strengths are stored between the passes when the context allows it and
-    // the memory for them can be had; the 5x5 first stage is built on the
-    // stored strengths only, so it always asks for them
+    // the memory for them can be had; the 5x5 first stage and the median
+    // cascade are built on the stored strengths only, so they always ask
+    // for them (and the cascade for a byte per pixel between its levels)
     c.storez = false;
-    if (need_out && (ctx->store_z || c.pl.std5)) {
+    const bool need_z = c.pl.std5 || c.pl.ncas > 0;
+    if (need_out && (ctx->store_z || need_z)) {
         long long px = 0;
         for (int i = 0; i < n; ++i) px += (long long)imgs[i].height * imgs[i].width;
         c.storez = ensure_zmap(ctx, px, c.pl.path);
-        if (!c.storez && c.pl.std5)
-            return set_err(ctx, LOGFX_ENOMEM, "the 5x5 first deviation stage needs %lld bytes of device "
-                                              "memory for the crossing strengths", px * (c.pl.path == LOGFX_PATH_INT32 ? 8 : 16));
+        if (!c.storez && need_z)
+            return set_err(ctx, LOGFX_ENOMEM, "the 5x5 first deviation stage and the median cascade need "
+                                              "%lld bytes of device memory for the crossing strengths",
+                           px * (c.pl.path == LOGFX_PATH_INT32 ? 8 : 16));
+        if (c.pl.ncas > 0 && px > ctx->ccap) {
+            (void)hipFree(ctx->cmap);
+            ctx->cmap = nullptr;
+            ctx->ccap = 0;
+            if (hipMalloc(&ctx->cmap, (size_t)px) != hipSuccess) {
+                ctx->cmap = nullptr;
+                (void)hipGetLastError();
+                return set_err(ctx, LOGFX_ENOMEM, "the median cascade needs %lld bytes of device memory", px);
+            }
+            ctx->ccap = px;
+        }
     }
     const int bits0 = imgs[0].bits == 0 ? (imgs[0].dtype == LOGFX_U8 ? 8 : 16) : imgs[0].bits;
     c.n = n;
@@ -605,6 +636,12 @@ struct Launches {
     int path, ra, rb;
     bool dbg;
     bool storez;
+    // median cascade: further levels after pass 2 (pass 2 writes the
+    // scratch map when their number is odd, so the last level ends in the
+    // caller's outputs)
+    int ncas;
+    LevelArgs lev[3];
+    int halo2;
     // smoothing gate
     bool features;                 // pass 1 sums the cells; the features are finished after it
     bool gated;                    // the network decides the median per image before pass 2
@@ -679,7 +716,11 @@ hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int unti
             return e;
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    if (k.storez) return i32 ? launch_pass2z_i(k.p2.i, k.grid2, s) : launch_pass2z_d(k.p2.d, k.grid2, s);
+    if (k.storez) {
+        e = i32 ? launch_pass2z_i(k.p2.i, k.grid2, s) : launch_pass2z_d(k.p2.d, k.grid2, s);
+        for (int i = 0; i < k.ncas && e == hipSuccess; ++i) e = launch_median_level(k.lev[i], k.halo2, s);
+        return e;
+    }
     return i32 ? launch_pass2_i(k.ra, k.rb, k.p2.i, k.grid2, s)
                : launch_pass2_d(k.ra, k.rb, k.p2.d, k.grid2, s);
 }
@@ -725,6 +766,24 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
             k.flags = G.flags;
             if (k.path == LOGFX_PATH_INT32) k.p2.i.med_flags = G.flags;
             else k.p2.d.med_flags = G.flags;
+        }
+    }
+    k.halo2 = c.pl.std5 ? kHalo2Z5 : kHalo2Z;
+    k.ncas = c.storez ? c.pl.ncas : 0;
+    if (k.ncas > 0) {
+        // level i reads the scratch map iff an odd number of levels remain
+        uint8_t *first = k.ncas % 2 ? ctx->cmap : nullptr;
+        if (k.path == LOGFX_PATH_INT32) k.p2.i.out_map = first;
+        else k.p2.d.out_map = first;
+        for (int i = 0; i < k.ncas; ++i) {
+            LevelArgs &l = k.lev[i];
+            l.L = c.L;
+            l.rows = ctx->tiles.rows2;
+            l.median_size = c.pl.cas[i];
+            l.from_scratch = (k.ncas - i) % 2;
+            l.scratch = ctx->cmap;
+            l.med_flags = k.gated ? ctx->gate.flags : nullptr;
+            l.counts = i == k.ncas - 1 ? ctx->counts2 : nullptr;
         }
     }
     k.fin.L = c.L;
@@ -938,6 +997,7 @@ std::string tune_key(logfx_ctx *ctx, const Call &c, const logfx_params *p, const
       << "|" << (img0->dtype == LOGFX_U8 ? "u8" : "u16") << "|med"
       << (p->smooth != LOGFX_SMOOTH_NEVER ? p->median_size : 0) << (p->smooth == LOGFX_SMOOTH_GATE ? "g" : "")
       << "|" << (c.n > 1 ? "batch" : "single") << (c.pl.std5 ? "|s5" : "");
+    for (int i = 0; i < c.pl.ncas; ++i) k << (i == 0 ? "|c" : "") << c.pl.cas[i];
     return k.str();
 }
 
@@ -1013,6 +1073,7 @@ int logfx_destroy(logfx_ctx *ctx) {
             (void)hipEventDestroy(ctx->staged);
         }
         (void)hipFree(ctx->zmap);
+        (void)hipFree(ctx->cmap);
         (void)hipFree(ctx->partials);
         (void)hipFree(ctx->counts1);
         (void)hipFree(ctx->counts2);

@@ -127,6 +127,21 @@ struct Pass2Args {
     const void *zmap;       // strength pairs written by pass 1 (pass 2 on stored strengths)
     int std5;               // the 5x5 first stage: E_j also needs s5 > std5_max (stored strengths only)
     double thr600[2];       // 600 (std5_max / unit_j)^2, compared with 25 sum z^2 - (sum z)^2
+    uint8_t *out_map;       // or nullptr: output of image i at out_map + jobs[i].zoff, pitch W
+                            // (the first level of a median cascade; stored strengths only)
+};
+
+// One further level of the hybrid median cascade, on maps of 0/1 bytes,
+// with the tiling of the stored-strength pass 2 (halo 3, or 4 with the 5x5
+// first stage).
+struct LevelArgs {
+    Launch L;               // the call's images: output maps, tiling
+    int rows;               // rows per strip (pass 2's)
+    int median_size;        // 3 or 5
+    int from_scratch;       // 1: read the scratch maps, write the outputs; 0: the reverse
+    uint8_t *scratch;       // image i at scratch + jobs[i].zoff, pitch W
+    const int *med_flags;   // [nimg] or nullptr: images whose flag is 0 are copied unfiltered
+    int *counts;            // [total2][2] or nullptr: each tile's output count into counts[2 t + 1]
 };
 
 struct FinalizeArgs {
@@ -158,6 +173,8 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 // tile_out_width(kHalo2Z) columns, or tile_out_width(kHalo2Z5) with the 5x5
 // first stage (a.std5).
 hipError_t launch_pass2z_i(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t s, int *max_grid = nullptr);
+// One further median level (halo 3 or 4, as the pass 2 of the same call).
+hipError_t launch_median_level(const LevelArgs &a, int halo, hipStream_t s);
 hipError_t launch_pass2z_d(const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s, int *max_grid = nullptr);
 
 // LDS bytes of one workgroup.

@@ -30,6 +30,29 @@ typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 // Bits s .. s + 31 of the 64-bit word hi:lo.
 __device__ inline unsigned funnel(unsigned hi, unsigned lo, int s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 
+// Hybrid median (window M = 3 or 5) of the 32 pixels of a column word:
+// bit k of w1:w0 >> 2 is the centre of output row k, bits k .. k + 4 its
+// column window; the other columns come from the neighbouring lanes.
+template <int M>
+__device__ inline unsigned median_word(unsigned w0, unsigned w1) {
+    const unsigned c = funnel(w1, w0, 2);
+    const unsigned l0 = from_left(w0), l1 = from_left(w1);     // column x - 1
+    const unsigned r0 = from_right(w0), r1 = from_right(w1);   // column x + 1
+    if constexpr (M == 3) {
+        const unsigned p[4] = {funnel(l1, l0, 2), funnel(r1, r0, 2), funnel(w1, w0, 1), funnel(w1, w0, 3)};
+        const unsigned x[4] = {funnel(l1, l0, 1), funnel(r1, r0, 1), funnel(l1, l0, 3), funnel(r1, r0, 3)};
+        return hybrid_median_bits<3>(c, p, x);
+    } else {
+        const unsigned ll0 = from_left(l0), ll1 = from_left(l1);     // column x - 2
+        const unsigned rr0 = from_right(r0), rr1 = from_right(r1);   // column x + 2
+        const unsigned p[8] = {funnel(ll1, ll0, 2), funnel(l1, l0, 2), funnel(r1, r0, 2), funnel(rr1, rr0, 2),
+                               w0, funnel(w1, w0, 1), funnel(w1, w0, 3), funnel(w1, w0, 4)};
+        const unsigned x[8] = {ll0, rr0, funnel(l1, l0, 1), funnel(r1, r0, 1),
+                               funnel(l1, l0, 3), funnel(r1, r0, 3), funnel(ll1, ll0, 4), funnel(rr1, rr0, 4)};
+        return hybrid_median_bits<5>(c, p, x);
+    }
+}
+
 // Row sums of the 5x5 deviation (the 5x5 first stage, Sec. 4.1): the 3x3
 // row sums (s, q) of the pixel plus its neighbours two columns away.
 __device__ inline void dev_row5(double zl2, double zr2, double s, double q, double &s5, double &q5) {
@@ -71,6 +94,9 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         const int lo_lane = base < 0 ? -base : 0;
         const int hi_lane = min(max(W - 1 - base, 0), kWave - 1);
         const unsigned outm = outc ? ~0u : 0u;
+        // the output map: the caller's, or the scratch map of a median cascade
+        uint8_t *const obase = a.out_map ? a.out_map + J.zoff : J.out;
+        const long long opitch = a.out_map ? (long long)W : J.out_pitch;
 
         const double thr600_0 = a.thr600[0], thr600_1 = a.thr600[1];
         double Zs[2][NR] = {}, Zq[2][NR] = {};   // 3x3 deviation row sums of the last NR rows read
@@ -104,35 +130,18 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             // bit k of funnel(.., 2 + d): E row y0 + wb + k + d
             const unsigned c = funnel(w1, w0, 2);
             unsigned f;
-            if constexpr (M == 0) {
-                f = c;
-            } else {
-                const unsigned l0 = from_left(w0), l1 = from_left(w1);     // column x - 1
-                const unsigned r0 = from_right(w0), r1 = from_right(w1);   // column x + 1
-                if constexpr (M == 3) {
-                    const unsigned p[4] = {funnel(l1, l0, 2), funnel(r1, r0, 2), funnel(w1, w0, 1), funnel(w1, w0, 3)};
-                    const unsigned x[4] = {funnel(l1, l0, 1), funnel(r1, r0, 1), funnel(l1, l0, 3), funnel(r1, r0, 3)};
-                    f = hybrid_median_bits<3>(c, p, x);
-                } else {
-                    const unsigned ll0 = from_left(l0), ll1 = from_left(l1);     // column x - 2
-                    const unsigned rr0 = from_right(r0), rr1 = from_right(r1);   // column x + 2
-                    const unsigned p[8] = {funnel(ll1, ll0, 2), funnel(l1, l0, 2), funnel(r1, r0, 2), funnel(rr1, rr0, 2),
-                                           w0, funnel(w1, w0, 1), funnel(w1, w0, 3), funnel(w1, w0, 4)};
-                    const unsigned x[8] = {ll0, rr0, funnel(l1, l0, 1), funnel(r1, r0, 1),
-                                           funnel(l1, l0, 3), funnel(r1, r0, 3), funnel(ll1, ll0, 4), funnel(rr1, rr0, 4)};
-                    f = hybrid_median_bits<5>(c, p, x);
-                }
-            }
+            if constexpr (M == 0) f = c;
+            else f = median_word<M>(w0, w1);
             const unsigned rm = (n >= 32 ? ~0u : (1u << n) - 1u) & outm;
             ecnt += __popc(c & rm);
             fcnt += __popc(f & rm);
             // a wave-uniform row address plus the lane's column
-            GlobalU8 *orow = (GlobalU8 *)(J.out + (long long)(y0 + wb) * J.out_pitch);
+            GlobalU8 *orow = (GlobalU8 *)(obase + (long long)(y0 + wb) * opitch);
             if (outc) {
 #pragma unroll 8
                 for (int k = 0; k < n; ++k) {
                     orow[(unsigned)xc] = (uint8_t)__builtin_amdgcn_ubfe(f, k, 1);
-                    orow += J.out_pitch;
+                    orow += opitch;
                 }
             }
             elo = ehi;
@@ -248,6 +257,84 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
     });
 }
 
+// One further level of the median cascade: reads a 0/1 map (clamp-to-edge
+// rows and columns, which is how every level reads its input), collects
+// each lane's column in words as pass 2 does, and writes the hybrid median
+// (or, for an image the gate leaves unsmoothed, the map itself).
+template <int HL, int M>
+__global__ __launch_bounds__(256) void median_level_kernel(LevelArgs a) {
+    __shared__ int redc[8];
+    constexpr int OW = kWave - 2 * HL, TW = tile_out_width(HL);
+    constexpr int G = 6;
+    const int item = blockIdx.x;
+    const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
+    const ImageJob J = job_of(a.L, image);
+    const int H = (int)J.img.H, W = (int)J.img.W;
+    const int tile = item - J.base2, tx = tile % J.tiles_x2, ty = tile / J.tiles_x2;
+    const int x0 = tx * TW, y0 = ty * a.rows, Rv = min(a.rows, H - y0);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int xc = x0 + wave * OW - HL + lane;
+    const bool outc = lane >= HL && lane < HL + OW && xc < W;
+    const unsigned outm = outc ? ~0u : 0u;
+    const bool copy = a.med_flags && !a.med_flags[image];
+    uint8_t *const scr = a.scratch + J.zoff;
+    const uint8_t *const src = a.from_scratch ? scr : J.out;
+    uint8_t *const dst = a.from_scratch ? J.out : scr;
+    const long long spitch = a.from_scratch ? (long long)W : J.out_pitch;
+    const long long dpitch = a.from_scratch ? J.out_pitch : (long long)W;
+    const uint8_t *const scol = src + min(max(xc, 0), W - 1);
+
+    // bit k of elo (of ehi): input row y0 - 2 + wb + k (+ 32)
+    unsigned elo = 0, ehi = 0, fcnt = 0;
+    int wb = 0;
+    const int nrows = Rv + 4;   // input rows y0 - 2 .. y0 + Rv + 1
+    auto emit = [&](const int n) __attribute__((always_inline)) {
+        unsigned f = funnel(ehi, elo, 2);
+        if (!copy) f = M == 3 ? median_word<3>(elo, ehi) : median_word<5>(elo, ehi);
+        fcnt += __popc(f & (n >= 32 ? ~0u : (1u << n) - 1u) & outm);
+        GlobalU8 *orow = (GlobalU8 *)(dst + (long long)(y0 + wb) * dpitch);
+        if (outc) {
+#pragma unroll 8
+            for (int k = 0; k < n; ++k) {
+                orow[(unsigned)xc] = (uint8_t)__builtin_amdgcn_ubfe(f, k, 1);
+                orow += dpitch;
+            }
+        }
+        elo = ehi;
+        ehi = 0;
+        wb += 32;
+    };
+    auto put = [&](const int b, const uint8_t v) __attribute__((always_inline)) {
+        const int p = b - wb;
+        const unsigned m = v != 0 ? ~0u : 0u;
+        elo |= m & (p < 32 ? 1u << p : 0u);
+        ehi |= m & (p >= 32 ? 1u << (p - 32) : 0u);
+    };
+    int b0 = 0;
+    for (; b0 + G <= nrows; b0 += G) {
+        uint8_t q[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) q[k] = scol[(long long)min(max(y0 - 2 + b0 + k, 0), H - 1) * spitch];
+#pragma unroll
+        for (int k = 0; k < G; ++k) put(b0 + k, q[k]);
+        if (b0 + G - wb >= 36) emit(32);   // rows wb .. wb + 35 present
+    }
+    for (; b0 < nrows; ++b0) put(b0, scol[(long long)min(max(y0 - 2 + b0, 0), H - 1) * spitch]);
+    while (wb < Rv) emit(min(32, Rv - wb));
+
+    if (a.counts) {
+        const int fs = wave_sum((int)fcnt);
+        if (lane == 0) redc[threadIdx.x / kWave] = fs;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int k = 0; k < (int)(blockDim.x / kWave); ++k) t += redc[k];
+            a.counts[(long long)item * 2 + 1] = t;
+        }
+    }
+}
+
 template <class Acc, int MED, bool S5>
 hipError_t p2z5(const Pass2Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
     constexpr bool CAN_LOOP = MED >= 0;   // gated variants run one tile per workgroup
@@ -277,6 +364,17 @@ hipError_t launch_pass2z_i(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t
 }
 hipError_t launch_pass2z_d(const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s, int *max_grid) {
     return kern::p2z_any<double>(a, grid, s, max_grid);
+}
+hipError_t launch_median_level(const LevelArgs &a, int halo, hipStream_t s) {
+    const dim3 grid(a.L.total2), block(kTileWaves * kWave);
+    if (halo == kHalo2Z5) {
+        if (a.median_size == 3) hipLaunchKernelGGL((kern::median_level_kernel<kHalo2Z5, 3>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((kern::median_level_kernel<kHalo2Z5, 5>), grid, block, 0, s, a);
+    } else {
+        if (a.median_size == 3) hipLaunchKernelGGL((kern::median_level_kernel<kHalo2Z, 3>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((kern::median_level_kernel<kHalo2Z, 5>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace logfx

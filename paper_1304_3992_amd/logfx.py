@@ -51,7 +51,8 @@ class logfx_params(ctypes.Structure):
     _fields_ = [("mask", logfx_mask * 2), ("zc_thresh", ctypes.c_double),
                 ("std_mode", ctypes.c_int32), ("std_k", ctypes.c_double),
                 ("std5_max", ctypes.c_double), ("smooth", ctypes.c_int32),
-                ("median_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("median_size", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("median_cascade", ctypes.c_int32 * 3)]
 
 
 class logfx_tune_result(ctypes.Structure):
@@ -179,7 +180,7 @@ class Params:
     """Holds a logfx_params struct and keeps its tap arrays alive."""
 
     def __init__(self, taps1, taps2, *, zc_thresh=0.0, std_mode=STD_REL, std_k=2.0,
-                 std5_max=-1.0, smooth=True, median_size=5, flags=0):
+                 std5_max=-1.0, smooth=True, median_size=5, flags=0, median_cascade=()):
         self.t1 = np.ascontiguousarray(taps1, dtype=np.float32)
         self.t2 = np.ascontiguousarray(taps2, dtype=np.float32)
         p = logfx_params()
@@ -194,6 +195,11 @@ class Params:
         p.smooth = smooth if not isinstance(smooth, bool) else (SMOOTH_ALWAYS if smooth else SMOOTH_NEVER)
         p.median_size = median_size
         p.flags = flags
+        cas = list(median_cascade)
+        if len(cas) > 3:
+            raise ValueError("at most 3 further median levels")
+        for i, m in enumerate(cas + [0] * (3 - len(cas))):
+            p.median_cascade[i] = m
         self.c = p
 
 

@@ -80,12 +80,14 @@ def dilate(mask: np.ndarray, r: int) -> np.ndarray:
     return out
 
 
-def compare(F_gpu: np.ndarray, orc, *, smooth: bool, median_size: int = 5, std5_max: float = -1.0) -> dict:
-    """Checks the band rule and returns counts."""
+def compare(F_gpu: np.ndarray, orc, *, smooth: bool, median_size: int = 5, std5_max: float = -1.0,
+            radius: int | None = None) -> dict:
+    """Checks the band rule and returns counts.  radius: how far a band
+    pixel's decision reaches into the output (default: the median's)."""
     b = band(orc, std5_max)
     ref = orc["F"]
     mism = F_gpu != ref
-    excused = dilate(b, median_size // 2 if smooth else 0)
+    excused = dilate(b, radius if radius is not None else (median_size // 2 if smooth else 0))
     unexcused = int((mism & ~excused).sum())
     n = ref.size
     info = {"mismatch": int(mism.sum()), "unexcused": unexcused, "band": int(b.sum()), "n": n}

@@ -321,3 +321,25 @@ def test_gated_batch_same_with_stored_or_recomputed_strengths(ctx, median_size):
         single = ctx.extract(d, logfx.Params(*lib_t, smooth=bool(r["smoothed"]), median_size=median_size),
                              bits=11).cpu().numpy()
         assert np.array_equal(o, single)
+
+
+def test_gate_decides_the_median_cascade(ctx):
+    """With further median levels the gate's choice covers all of them: a
+    smoothed image gets every level, an unsmoothed one none (its map passes
+    the levels unchanged)."""
+    import torch
+    tiles = _gate_tiles()[:3]
+    _, lib_t = masks()
+    devs = [to_device(t) for t in tiles]
+    cas = (3, 5)
+    always = ctx.extract_batch(devs, logfx.Params(*lib_t, smooth=True, median_cascade=cas), bits=11)
+    never = ctx.extract_batch(devs, logfx.Params(*lib_t, smooth=False), bits=11)
+    gparams = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, median_cascade=cas)
+    theta = og.init(102)
+    for bias, ref in ((50.0, always), (-50.0, never)):
+        theta[og.NPARAM - 1] = bias
+        ctx.gate_set_params(theta)
+        outs = ctx.extract_batch(devs, gparams, bits=11)
+        torch.cuda.synchronize()
+        for o, e in zip(outs, ref):
+            assert torch.equal(o, e)

@@ -282,3 +282,88 @@ def test_first_stage_5x5_batch_and_recompute_setting(ctx):
         assert torch.equal(b, s), i
         o = run_oracle(tiles[i], orc_t, std5_max=t)
         compare(s.cpu().numpy(), o, smooth=True, std5_max=t)
+
+
+def _midpoint(values, q):
+    """Halfway between two neighbouring distinct values near quantile q."""
+    v = np.unique(values)
+    k = min(int(q * (v.size - 1)), v.size - 2)
+    return float(0.5 * (v[k] + v[k + 1]))
+
+
+@pytest.mark.parametrize("smooth", [True, False])
+def test_paper_rule_and_masks(ctx, smooth):
+    """The paper's own configuration (Sec. 4.1): two 5x5 masks of variance
+    0.5 and 20, a zero-crossing threshold (Sec. 3.2), the 5x5 first stage
+    and the 3x3 test with absolute thresholds.  Thresholds are taken halfway
+    between neighbouring oracle values so that no pixel sits on one."""
+    img = scenes.config1()
+    orc_t, lib_t = masks(((5, 0.5 ** 0.5), (5, 20 ** 0.5)), 16)
+    o0 = run_oracle(img, orc_t)
+    z = np.concatenate([o0["Z1"][o0["Z1"] > 0], o0["Z2"][o0["Z2"] > 0]])
+    zc = _midpoint(z, 0.3)
+    o1 = run_oracle(img, orc_t, zc_thresh=zc)
+    s3 = np.concatenate([o1["S1"][o1["S1"] > 0], o1["S2"][o1["S2"] > 0]])
+    kw = dict(zc_thresh=zc, std_mode=logfx.STD_ABS, std_k=_midpoint(s3, 0.7))
+    o2 = run_oracle(img, orc_t, **kw)
+    s5 = np.maximum(oracle.local_std(o2["Z1"], 5), oracle.local_std(o2["Z2"], 5))
+    kw["std5_max"] = _midpoint(s5[o2["E"] > 0], 0.4)
+    o = run_oracle(img, orc_t, smooth=smooth, **kw)
+    F, rep = run_gpu(ctx, img, lib_t, smooth=smooth, **kw)
+    info = compare(F, o, smooth=smooth, std5_max=kw["std5_max"])
+    assert rep["zc_count"] == [int((o["Z1"] != 0).sum()), int((o["Z2"] != 0).sum())]
+    assert abs(rep["extracted"] - int(o["E"].sum())) <= info["band"]
+    assert 0 < o["E"].sum() < o2["E"].sum()   # every stage is active
+
+
+CASCADE_CASES = [
+    ("c1_5_3", lambda: scenes.config1(), 0, dict(median_cascade=(3,))),
+    ("c1_5_3_5", lambda: scenes.config1(), 0, dict(median_cascade=(3, 5))),
+    ("c1_3_5_3_5", lambda: scenes.config1(), 0, dict(median_size=3, median_cascade=(5, 3, 5))),
+    ("ragged_u11_5_3", lambda: _scene_crop(257, 449, 13, 11), 11, dict(median_cascade=(3,))),
+    ("ragged_u8_5_5", lambda: _scene_crop(700, 333, 12), 0, dict(median_cascade=(5,))),
+    ("tiny_2x2", lambda: _rand((2, 2), 255, 15, np.uint8), 0, dict(median_cascade=(5, 3))),
+    ("row_1x300", lambda: _rand((1, 300), 255, 16, np.uint8), 0, dict(median_cascade=(3,))),
+    ("col_300x1", lambda: _rand((300, 1), 255, 17, np.uint8), 0, dict(median_cascade=(5, 3))),
+    ("nosmooth_ignored", lambda: scenes.config1(), 0, dict(smooth=False, median_cascade=(3, 5))),
+]
+
+
+@pytest.mark.parametrize("name,make,bits,kw", CASCADE_CASES, ids=[c[0] for c in CASCADE_CASES])
+def test_median_cascade(ctx, name, make, bits, kw):
+    """Further hybrid median levels (Sec. 3.4 / Sec. 4.2): the output equals
+    the oracle's single-level output filtered again by the oracle's hybrid
+    median with each further window, level by level; band pixels excuse
+    mismatches within the summed radius of all levels."""
+    img = make()
+    orc_t, lib_t = masks()
+    cas = kw.pop("median_cascade")
+    smooth = kw.get("smooth", True)
+    o = run_oracle(img, orc_t, **kw)
+    ref = o["F"]
+    radius = kw.get("median_size", 5) // 2 if smooth else 0
+    if smooth:
+        for m in cas:
+            ref = oracle.hybrid_median(ref, m)
+            radius += m // 2
+    F, rep = run_gpu(ctx, img, lib_t, bits=bits, median_cascade=cas, **kw)
+    compare(F, dict(o, F=ref), smooth=smooth, radius=radius)
+    assert rep["output"] == int(F.sum())
+
+
+def test_median_cascade_batch_equals_singles(ctx):
+    """A batch with two further levels gives each tile its single-call
+    output (the levels ping-pong between the outputs and the context's
+    scratch map, image by image)."""
+    import torch
+    tiles = scenes.config3(n=6, seed=79, base_seed=7900, lo=60, hi=600)
+    _, lib_t = masks()
+    for cas in ((3,), (3, 5)):
+        params = logfx.Params(*lib_t, median_cascade=cas)
+        devs = [to_device(x) for x in tiles]
+        outs, reps = ctx.extract_batch(devs, params, bits=8, report=True)
+        for i, d in enumerate(devs):
+            s, r = ctx.extract(d, params, bits=8, report=True)
+            torch.cuda.synchronize()
+            assert torch.equal(outs[i], s), (cas, i)
+            assert reps[i]["output"] == r["output"] == int(s.sum().item())
