@@ -62,9 +62,9 @@ PASS2Z_OPS_PER_PX = 2 * 12 + 3
 # (scaled by a plain copy of known size; profiles/pipeline_kernels_8192x8192_u16.md)
 # for the kernel sources with this hash.  Reported only while the sources are
 # unchanged.
-TRAFFIC_SOURCE_HASH = "8e9c06f838811756"
-TRAFFIC_BYTES = {"pass1_kernel": (69013 * 2.0 + 525259 * 1.0) * 1024,
-                 "pass2z_kernel": (296632 * 2.0 + 81683 * 1.0) * 1024}
+TRAFFIC_SOURCE_HASH = "de26c14e077b1856"
+TRAFFIC_BYTES = {"pass1_kernel": (69009 * 2.0 + 525238 * 1.0) * 1024,
+                 "pass2z_kernel": (296472 * 2.0 + 81734 * 1.0) * 1024}
 # Algorithmic HBM bytes per pixel of each kernel: pass 1 reads the 16-bit
 # image and writes the (Z_1, Z_2) int32 pair; pass 2 reads the pair and
 # writes the output byte.
@@ -220,6 +220,8 @@ def main():
                     help="skip the autotuner (strip heights stay at their defaults)")
     ap.add_argument("--store-z", type=int, default=1, choices=[0, 1],
                     help="1: pass 2 reads the strengths pass 1 stored (default); 0: recomputes them")
+    ap.add_argument("--median-cascade", default="",
+                    help="further hybrid median windows after the first, e.g. 3,5 (default: none)")
     ap.add_argument("--workload", choices=["scene", "gated"], default="scene",
                     help="scene: the 8192^2 scene (default); gated: the gate's four-band workload")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -245,7 +247,8 @@ def main():
     img = scenes.config2(size=args.size)
     H, W = img.shape
     lib_taps = (logfx.make_log_mask(5, 0.8, 16)[0], logfx.make_log_mask(9, 1.4, 16)[0])
-    params = logfx.Params(*lib_taps, std_k=2.0, smooth=True, median_size=5)
+    cascade = tuple(int(m) for m in args.median_cascade.split(",") if m)
+    params = logfx.Params(*lib_taps, std_k=2.0, smooth=True, median_size=5, median_cascade=cascade)
 
     dev = torch.device("cuda", 0)
     host = torch.from_numpy(img.view(np.int16))
@@ -319,7 +322,8 @@ def main():
         "dtype": "int32" if rep["path"] == logfx.PATH_INT32 else "f64", "data": "synthetic",
         "config": {"workload": f"{H}x{W} uint16 11-bit scene (20000 rectangles, 500 polylines, "
                                "noise sigma 12, 5% salt-and-pepper); LoG 5x5 s0.8 + 9x9 s1.4; "
-                               "3x3 deviation > 2.0 global; 5x5 hybrid median",
+                               "3x3 deviation > 2.0 global; 5x5 hybrid median"
+                               + "".join(f", then {m}x{m}" for m in cascade),
                    "pixels": px, "parallelism": "single GPU", "store_z": args.store_z,
                    "rows_per_strip": [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]},
         "kernels_ms": {"pass1": round(avg[0], 4), "finalize": round(avg[1], 4),
