@@ -285,6 +285,29 @@ def main():
     kern_ms, calls = ctx.timing_read()
     ctx.timing_enable(False)
     ms_step = total_ms / args.steps
+    # spread of single steps (after the timed region, not part of `value`)
+    singles = []
+    for i in range(min(args.steps, 30)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.extract(bufs[i % 3], params, out, bits=11)
+        e1.record(stream)
+        singles.append((e0, e1))
+    torch.cuda.synchronize()
+    step_ms = np.array([a.elapsed_time(b) for a, b in singles])
+    # a plain device copy of 1 GiB: the HBM bandwidth this machine reaches
+    csrc = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        cdst.copy_(csrc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del csrc, cdst
     px = H * W
     value = px / (ms_step * 1e-3) / 1e6
     avg = [k / max(calls, 1) for k in kern_ms]
@@ -311,6 +334,13 @@ def main():
                         "achieved_GBs": round(KERNEL_BYTES_PER_PX[dom_name] * px / (avg[dom] * 1e-3) / 1e9, 1),
                         "frac": round(KERNEL_BYTES_PER_PX[dom_name] * px / (avg[dom] * 1e-3) / 1e9
                                       / HBM_PEAK_GBS, 4)} if dom_name in KERNEL_BYTES_PER_PX else None),
+        "measured_copy_GBs": round(copy_gbs, 1),
+        "pass2_hbm": ({"kernel": "pass2z_kernel", "bytes_per_pixel": KERNEL_BYTES_PER_PX["pass2z_kernel"],
+                       "achieved_GBs": round(KERNEL_BYTES_PER_PX["pass2z_kernel"] * px / (avg[2] * 1e-3) / 1e9, 1),
+                       "frac_peak": round(KERNEL_BYTES_PER_PX["pass2z_kernel"] * px / (avg[2] * 1e-3) / 1e9
+                                          / HBM_PEAK_GBS, 4),
+                       "frac_copy": round(KERNEL_BYTES_PER_PX["pass2z_kernel"] * px / (avg[2] * 1e-3) / 1e9
+                                          / copy_gbs, 4)} if stored else None),
         "hbm_view": {"bytes_per_pixel": 3, "achieved_GBs": round(3 * px / (ms_step * 1e-3) / 1e9, 1),
                      "peak_GBs": HBM_PEAK_GBS,
                      "frac": round(3 * px / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
@@ -328,6 +358,7 @@ def main():
                    "rows_per_strip": [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]},
         "kernels_ms": {"pass1": round(avg[0], 4), "finalize": round(avg[1], 4),
                        "pass2": round(avg[2], 4)},
+        "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
         "roofline": roofline,
     }
     ctx.close()
