@@ -98,6 +98,7 @@ def host_cores() -> int:
 def cpu_baseline(img, orc_taps, min_seconds: float = 10.0):
     """The oracle, as it stands, on the host cores: whole-scene runs repeated
     until at least min_seconds have passed."""
+    import numpy as np
     import oracle
     n = host_cores()
     runs, t0 = 0, time.perf_counter()
@@ -115,7 +116,7 @@ def cpu_baseline(img, orc_taps, min_seconds: float = 10.0):
     t0 = time.perf_counter()
     oracle.extract(crop, orc_taps[0], orc_taps[1], nthreads=1)
     res["value_1_thread"] = crop.size / (time.perf_counter() - t0) / 1e6
-    res["sample_1_thread"] = "2048x2048 crop of the scene, 1 run"
+    res["sample_1_thread"] = f"{crop.shape[0]}x{crop.shape[1]} crop of the scene, 1 run"
     return res
 
 
