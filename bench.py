@@ -218,6 +218,69 @@ def bench_gated(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_batch(args):
+    """The 64 uneven tiles (sides log-uniform in [256, 4096]) as one batch
+    call: the tuner's choice, each launch form, and the same tiles as single
+    calls for comparison."""
+    import numpy as np
+    import torch
+    from paper_1304_3992_amd import logfx, scenes
+    tiles = scenes.config3()
+    px = sum(t.size for t in tiles)
+    devs = [torch.from_numpy(t.view(np.int16)).cuda() for t in tiles]
+    outs = [torch.empty(t.shape, dtype=torch.uint8, device="cuda") for t in tiles]
+    params = logfx.Params(logfx.make_log_mask(5, 0.8, 16)[0], logfx.make_log_mask(9, 1.4, 16)[0])
+    ctx = logfx.Context(0)
+    stream = torch.cuda.current_stream()
+    if not args.no_tune:
+        ctx.tune(devs, params, outs, bits=8, reps=3)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    ms = timed(lambda: ctx.extract_batch(devs, params, outs, bits=8))
+    chosen = {"persistent": ctx.get_option(logfx.OPT_PERSISTENT), "graph": ctx.get_option(logfx.OPT_GRAPH),
+              "rows": [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]}
+    forms = {}
+    for pers in (0, 1):
+        for graph in (0, 1):
+            ctx.set_option(logfx.OPT_PERSISTENT, pers)
+            ctx.set_option(logfx.OPT_GRAPH, graph)
+            forms[f"persistent{pers}_graph{graph}"] = round(
+                timed(lambda: ctx.extract_batch(devs, params, outs, bits=8)), 4)
+    ctx.set_option(logfx.OPT_PERSISTENT, chosen["persistent"])
+    ctx.set_option(logfx.OPT_GRAPH, chosen["graph"])
+
+    def singles():
+        for d, o in zip(devs, outs):
+            ctx.extract(d, params, o, bits=8)
+    single_ms = timed(singles)
+    ctx.close()
+    log(f"batch: {ms:.3f} ms, single calls: {single_ms:.3f} ms, forms {forms}")
+    result = {
+        "metric": METRIC, "value": round(px / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "64 uint16 tiles, sides log-uniform in [256, 4096] (seed 3), uint8 values, "
+                               "40 rectangles per 512^2, noise sigma 4; LoG 5x5 s0.8 + 9x9 s1.4; "
+                               "3x3 deviation > 2.0 global per tile; 5x5 hybrid median; one batch call",
+                   "pixels": px, "tiles": len(tiles), "parallelism": "single GPU", "launch": chosen},
+        "launch_forms_ms": forms,
+        "single_calls": {"ms_per_step": round(single_ms, 4),
+                         "Mpixel_s": round(px / (single_ms * 1e-3) / 1e6, 1)},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,8 +294,9 @@ def main():
                     help="1: pass 2 reads the strengths pass 1 stored (default); 0: recomputes them")
     ap.add_argument("--median-cascade", default="",
                     help="further hybrid median windows after the first, e.g. 3,5 (default: none)")
-    ap.add_argument("--workload", choices=["scene", "gated"], default="scene",
-                    help="scene: the 8192^2 scene (default); gated: the gate's four-band workload")
+    ap.add_argument("--workload", choices=["scene", "gated", "batch"], default="scene",
+                    help="scene: the 8192^2 scene (default); gated: the gate's four-band workload; "
+                         "batch: 64 uneven tiles in one call")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -244,6 +308,8 @@ def main():
         sys.exit(2)
     if args.workload == "gated":
         return bench_gated(args)
+    if args.workload == "batch":
+        return bench_batch(args)
 
     import numpy as np
     import torch
