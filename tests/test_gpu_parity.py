@@ -88,6 +88,9 @@ EXTRACT_CASES = [
     ("saturated", lambda: (np.random.default_rng(19).random((120, 140)) < 0.5).astype(np.uint16)
      * 65535, 16, {}),
     ("constant", lambda: np.full((100, 100), 33, np.uint8), 0, {}),
+    ("wide_9x180000", lambda: _rand((9, 180000), 255, 22, np.uint8), 0, {}),
+    ("tall_180000x9", lambda: _rand((180000, 9), 255, 23, np.uint8), 0, {}),
+    ("wide_u11_5x70001", lambda: _scene_crop(5, 70001, 24, 11), 11, dict(median_size=3)),
 ]
 
 
@@ -187,6 +190,23 @@ def test_config2_full_size(ctx):
             assert np.array_equal(g[r0:r0 + 70].cpu().numpy(), o[k][r0:r0 + 70]), (k, r0)
     del maps
     print("config2", info)
+
+
+def test_largest_single_image_16400(ctx):
+    """A 16400^2 image in one call: 269 Mpixel, 2.15 GB of stored strength
+    pairs (byte offsets past 2^31), 67 x 257 pass-1 tiles; the whole output
+    against the oracle with the band rule."""
+    import torch
+    img = _rand((16400, 16400), 2047, 25, np.uint16)
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t)
+    F, rep = run_gpu(ctx, img, lib_t, bits=11)
+    info = compare(F, o, smooth=True)
+    assert rep["output"] == int(F.sum())
+    np.testing.assert_allclose(rep["sigma_g"], o["stats"][:2], rtol=1e-12)
+    del o, F
+    torch.cuda.empty_cache()
+    print("16384^2", info)
 
 
 @pytest.mark.parametrize("name,make,bits,kw", [c for c in EXTRACT_CASES if c[0] in
