@@ -98,7 +98,10 @@ typedef struct {
  *   smooth     : LOGFX_SMOOTH_NEVER, LOGFX_SMOOTH_ALWAYS (hybrid median) or
  *                LOGFX_SMOOTH_GATE (the gate chooses per image).
  *   median_size: 3 or 5 (window of the hybrid median, Sec. 3.4).
- *   flags      : reserved, must be 0.
+ *   flags      : 0, or LOGFX_ALLOW_INEXACT: a mask pair whose taps cannot
+ *                be summed exactly in FP64 (LOGFX_EUNSUPPORTED without the
+ *                flag) runs on the FP64 path with rounded sums, and the
+ *                report says so (inexact = 1).  Other bits: LOGFX_EINVAL.
  *   median_cascade: further levels of the hybrid median (Sec. 3.4: the
  *                filter may be applied repeatedly; Sec. 4.2: the map passes
  *                through levels of larger and smaller windows).  Entry i,
@@ -109,6 +112,8 @@ typedef struct {
  *                the gate smooths).  Calls with further levels store the
  *                strengths between the passes whatever LOGFX_OPT_STORE_Z
  *                says and keep a 1-byte-per-pixel map in the context. */
+#define LOGFX_ALLOW_INEXACT 1u
+
 typedef struct {
     logfx_mask mask[2];
     double zc_thresh;
@@ -135,6 +140,7 @@ typedef struct {
     int32_t gated;        /* 1 if the gate took the smoothing decision     */
     int32_t gate_fallback;/* 1 if GATE was asked with no gate parameters   */
     double gate_logit;    /* the gate's logit (gated calls), else 0        */
+    int32_t inexact;      /* 1 if the LoG sums were rounded (LOGFX_ALLOW_INEXACT) */
 } logfx_report;
 
 /* Library version string (static storage). */

@@ -303,7 +303,7 @@ struct MaskInfo {
     double maxabs = 0.0;     // max |k|
 };
 
-int analyze_mask(logfx_ctx *ctx, const logfx_mask &m, int which, MaskInfo &mi) {
+int analyze_mask(logfx_ctx *ctx, const logfx_mask &m, int which, MaskInfo &mi, bool inexact_ok) {
     if (!m.taps) return set_err(ctx, LOGFX_EINVAL, "mask %d: taps is NULL", which);
     if (m.size < 1 || m.size % 2 == 0 || m.size > 15)
         return set_err(ctx, LOGFX_EINVAL, "mask %d: size %d is not odd in 1..15", which, m.size);
@@ -332,9 +332,10 @@ int analyze_mask(logfx_ctx *ctx, const logfx_mask &m, int which, MaskInfo &mi) {
     mi.sumabs = mi.maxabs = 0.0;
     for (int i = 0; i < s * s; ++i) {
         const double k = (double)m.taps[i] / mi.unit;
-        if (std::fabs(k) > 9007199254740992.0)
+        if (std::fabs(k) > 9007199254740992.0 && !inexact_ok)
             return set_err(ctx, LOGFX_EUNSUPPORTED,
-                           "mask %d: taps span too many binary orders for exact sums", which);
+                           "mask %d: taps span too many binary orders for exact sums "
+                           "(LOGFX_ALLOW_INEXACT runs them with rounded sums)", which);
         mi.k[i] = k;
         mi.sumabs += std::fabs(k);
         if (std::fabs(k) > mi.maxabs) mi.maxabs = std::fabs(k);
@@ -361,6 +362,7 @@ struct Plan {
     int path = LOGFX_PATH_INT32;
     double maxpix = 255.0;
     bool std5 = false;    // the 5x5 first deviation stage is on (std5_max >= 0)
+    bool inexact = false; // the FP64 LoG sums round (LOGFX_ALLOW_INEXACT)
     int ncas = 0;         // further median levels (applied where the first level is)
     int cas[3] = {0, 0, 0};
 };
@@ -390,7 +392,8 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
         return set_err(ctx, LOGFX_EINVAL, "unknown smooth mode %d", p->smooth);
     if (p->median_size != 3 && p->median_size != 5)
         return set_err(ctx, LOGFX_EINVAL, "median_size %d is not 3 or 5", p->median_size);
-    if (p->flags != 0) return set_err(ctx, LOGFX_EINVAL, "flags must be 0");
+    if ((p->flags & ~LOGFX_ALLOW_INEXACT) != 0)
+        return set_err(ctx, LOGFX_EINVAL, "flags 0x%x: only LOGFX_ALLOW_INEXACT is defined", p->flags);
     for (int i = 0; i < 3; ++i) {
         const int m = p->median_cascade[i];
         if (m != 0 && m != 3 && m != 5)
@@ -400,7 +403,8 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     }
     int rc;
     for (int j = 0; j < 2; ++j)
-        if ((rc = analyze_mask(ctx, p->mask[j], j, pl.mi[j])) != LOGFX_OK) return rc;
+        if ((rc = analyze_mask(ctx, p->mask[j], j, pl.mi[j], (p->flags & LOGFX_ALLOW_INEXACT) != 0)) != LOGFX_OK)
+            return rc;
     pl.maxpix = std::ldexp(1.0, bits) - 1.0;
     bool int_ok = true, f64_ok = true;
     for (int j = 0; j < 2; ++j) {
@@ -408,10 +412,12 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
         if (!(bound < 1073741824.0 && pl.mi[j].maxabs < 8388608.0)) int_ok = false;  // 2^30, 2^23
         if (!(bound < 4503599627370496.0)) f64_ok = false;                              // 2^52
     }
-    if (!f64_ok)
+    pl.inexact = !f64_ok;
+    if (!f64_ok && !(p->flags & LOGFX_ALLOW_INEXACT))
         return set_err(ctx, LOGFX_EUNSUPPORTED,
                        "mask taps are not exactly summable for %d-bit pixels "
-                       "(sum|k| * (2^bits - 1) must stay below 2^52)", bits);
+                       "(sum|k| * (2^bits - 1) must stay below 2^52; LOGFX_ALLOW_INEXACT runs "
+                       "them with rounded sums)", bits);
     pl.path = int_ok ? LOGFX_PATH_INT32 : LOGFX_PATH_FP64;
     const int r0 = pl.mi[0].radius, r1 = pl.mi[1].radius;
     if (r0 <= r1) pl.order[0] = 0, pl.order[1] = 1;
@@ -890,6 +896,7 @@ int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, const Lau
         }
         b2 += c.tiles[i].ntiles2;
         r.path = c.pl.path;
+        r.inexact = c.pl.inexact ? 1 : 0;
         r.smoothed = p->smooth != LOGFX_SMOOTH_NEVER;
         if (k.gated) {
             r.gated = 1;

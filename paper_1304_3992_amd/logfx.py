@@ -30,6 +30,7 @@ EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_gate_step", "logfx_gate"]
 GATE_NPARAM, GATE_CELLS, GATE_MAX_BATCH = 14369, 128, 4096
 OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH, OPT_STORE_Z = 1, 2, 3, 4, 5
+ALLOW_INEXACT = 1
 
 
 class LogfxError(RuntimeError):
@@ -67,14 +68,14 @@ class logfx_report(ctypes.Structure):
                 ("extracted", ctypes.c_int64), ("output", ctypes.c_int64),
                 ("path", ctypes.c_int32), ("smoothed", ctypes.c_int32),
                 ("gated", ctypes.c_int32), ("gate_fallback", ctypes.c_int32),
-                ("gate_logit", ctypes.c_double)]
+                ("gate_logit", ctypes.c_double), ("inexact", ctypes.c_int32)]
 
     def as_dict(self):
         return {"pixels": self.pixels, "sigma_g": list(self.sigma_g), "thresh": list(self.thresh),
                 "zc_count": list(self.zc_count), "extracted": self.extracted,
                 "output": self.output, "path": self.path, "smoothed": self.smoothed,
                 "gated": self.gated, "gate_fallback": self.gate_fallback,
-                "gate_logit": self.gate_logit}
+                "gate_logit": self.gate_logit, "inexact": self.inexact}
 
 
 _lib = None

@@ -106,7 +106,10 @@ def test_check_params_rejections(lib):
     assert _rc(_img(), _params(zc_thresh=float("nan")))[0] == E
     assert _rc(_img(), _params(median_size=4))[0] == E
     assert _rc(_img(), _params(std_mode=3))[0] == E
-    assert _rc(_img(), _params(flags=1))[0] == E
+    assert _rc(_img(), _params(flags=2))[0] == E
+    assert _rc(_img(), _params(median_cascade=(3, 4)))[0] == E
+    assert _rc(_img(), _params(median_cascade=(0, 3)))[0] == E
+    assert _rc(_img(), _params(median_cascade=(5, 3, 5)))[0] == logfx.OK
     assert _rc(_img(), _params(std5_max=float("nan")))[0] == E
     assert _rc(_img(), _params(std5_max=2.0)) == (logfx.OK, logfx.PATH_INT32)   # the 5x5 first stage
     p = _params()
@@ -188,3 +191,24 @@ def test_gate_entry_points_reject_null_context(lib):
     assert lib.logfx_gate_backward(None, 1, None, None, None, None, None, None) == E
     assert lib.logfx_gate_step(None, None, 1e-3, None) == E
     assert "ctx is NULL" in logfx.last_error()
+
+
+def _wide_range_masks():
+    """The benchmark masks with corner taps of 1e-30: exact FP64 sums would
+    need integers far beyond 2^52."""
+    m1 = logfx.make_log_mask(5, 0.8)[0].copy()
+    m2 = logfx.make_log_mask(9, 1.4)[0].copy()
+    for m in (m1, m2):
+        n = m.shape[0] - 1
+        m[0, 0] = m[0, n] = m[n, 0] = m[n, n] = np.float32(1e-30)
+    return m1, m2
+
+
+def test_allow_inexact_flag(lib):
+    """Masks whose taps cannot be summed exactly are refused, unless
+    LOGFX_ALLOW_INEXACT is set: then they run on the FP64 path."""
+    m1, m2 = _wide_range_masks()
+    assert _rc(_img(), logfx.Params(m1, m2))[0] == logfx.EUNSUPPORTED
+    assert _rc(_img(), logfx.Params(m1, m2, flags=logfx.ALLOW_INEXACT)) == (logfx.OK, logfx.PATH_FP64)
+    # exact masks are unaffected by the flag
+    assert _rc(_img(), _params(flags=logfx.ALLOW_INEXACT)) == (logfx.OK, logfx.PATH_INT32)

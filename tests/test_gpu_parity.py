@@ -387,3 +387,25 @@ def test_median_cascade_batch_equals_singles(ctx):
             torch.cuda.synchronize()
             assert torch.equal(outs[i], s), (cas, i)
             assert reps[i]["output"] == r["output"] == int(s.sum().item())
+
+
+def test_allow_inexact_masks(ctx):
+    """With LOGFX_ALLOW_INEXACT a mask pair of very wide dynamic range runs
+    on the FP64 path: the LoG responses agree with the oracle's within
+    1e-5 of sum |m| |x| (the oracle's FP64 sums round too), the output maps
+    nearly everywhere, and the report says the sums were rounded."""
+    import torch
+    from test_abi import _wide_range_masks
+    img = scenes.config1()
+    m1, m2 = _wide_range_masks()
+    params = logfx.Params(m1, m2, flags=logfx.ALLOW_INEXACT)
+    maps = ctx.extract_maps(to_device(img), params)
+    F, rep = run_gpu(ctx, img, (m1, m2), flags=logfx.ALLOW_INEXACT)
+    torch.cuda.synchronize()
+    assert rep["inexact"] == 1 and rep["path"] == logfx.PATH_FP64
+    for k, m in (("L1", m1), ("L2", m2)):
+        ref = oracle.log_response(img, m)
+        scale = oracle.log_response(img, np.abs(m))   # sum |m| |x| (pixels are >= 0)
+        assert np.all(np.abs(maps[k].cpu().numpy() - ref) <= 1e-5 * scale), k
+    o = run_oracle(img, (m1, m2))
+    assert (F != o["F"]).mean() <= 1e-4
