@@ -65,6 +65,10 @@ __host__ __device__ constexpr int tile_lds_offset(int halo, int rb) { return (8 
 __host__ __device__ constexpr int tile_lds_stride(int halo, int rb) {
     return (tile_out_width(halo) + 2 * halo + 2 * rb + tile_lds_offset(halo, rb) + 7) / 8 * 8;
 }
+// The staging loads of the passes that read the image copy 8 pixels at a
+// time from the tile origin, so their tiles must be 8-multiples wide.
+static_assert(tile_out_width(kHalo1) % 8 == 0 && tile_out_width(kHalo2) % 8 == 0,
+              "image-reading passes need 8-multiple tile widths");
 
 // One image of a launch: its input, its output and where its tiles sit in
 // the launch's tile list.

@@ -416,6 +416,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     __shared__ unsigned cellv[(MODE & kP1Cells) != 0 ? tile_out_width(kHalo1) : 1];
     __shared__ unsigned cellc[(MODE & kP1Cells) != 0 ? tile_out_width(kHalo1) : 1];
     constexpr int HL = kHalo1, P = 2 * RB + 1;
+    // The step schedule below takes one halo row above and below the strip:
+    // the crossing row r = t - 1 is an output row from the third step to the
+    // last.  A wider halo would store rows outside the strip (and, at the
+    // image's top and bottom, outside the strength map).
+    static_assert(HL == 1, "pass 1 steps assume a one-row halo");
 
     for_each_tile<LOOP>(a.L.total1, [&](const int item) __attribute__((always_inline)) {
     const ImageJob J = job_of(a.L, a.L.nimg == 1 ? 0 : a.L.owner1[item]);
