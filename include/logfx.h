@@ -111,7 +111,23 @@ typedef struct {
  *                (LOGFX_SMOOTH_ALWAYS, or LOGFX_SMOOTH_GATE on the images
  *                the gate smooths).  Calls with further levels store the
  *                strengths between the passes whatever LOGFX_OPT_STORE_Z
- *                says and keep a 1-byte-per-pixel map in the context. */
+ *                says and keep a 1-byte-per-pixel map in the context.
+ *   gate_region: 0, or the side R of the square regions in which the gate
+ *                decides the median of a single image (seamless scene
+ *                mode: a scene cut into tiles only for the smoothing
+ *                choice, which Sec. 1 makes per image).  The image keeps one
+ *                global deviation and threshold per mask and reads its
+ *                neighbours across region borders; each region gets the
+ *                gate's features of its own 128 x 128 cells and its own
+ *                decision, and its pixels are F where the region is
+ *                smoothed, E elsewhere.  Needs smooth = LOGFX_SMOOTH_GATE,
+ *                128 <= R < 2^23, height and width multiples of R, a
+ *                power-of-two number of regions across and down (at most
+ *                LOGFX_GATE_MAX_BATCH in all), no median_cascade, and a
+ *                single-image call (LOGFX_EINVAL otherwise).  Stores the
+ *                strengths between the passes whatever LOGFX_OPT_STORE_Z
+ *                says.  Without gate parameters the call falls back to
+ *                LOGFX_SMOOTH_ALWAYS, as GATE does. */
 #define LOGFX_ALLOW_INEXACT 1u
 
 typedef struct {
@@ -124,6 +140,7 @@ typedef struct {
     int32_t median_size;
     uint32_t flags;
     int32_t median_cascade[3];
+    int32_t gate_region;
 } logfx_params;
 
 /* Filled when a call is given a report (the call then waits for its
@@ -141,6 +158,8 @@ typedef struct {
     int32_t gate_fallback;/* 1 if GATE was asked with no gate parameters   */
     double gate_logit;    /* the gate's logit (gated calls), else 0        */
     int32_t inexact;      /* 1 if the LoG sums were rounded (LOGFX_ALLOW_INEXACT) */
+    int32_t regions;      /* gate_region calls: number of regions, else 0  */
+    int32_t regions_smoothed; /* of them, the regions the gate smoothed   */
 } logfx_report;
 
 /* Library version string (static storage). */
@@ -301,7 +320,9 @@ int logfx_timing_read(logfx_ctx *ctx, double *ms_out, int64_t *calls_out);
 /* Features of n images (pass 1 of the pipeline with the cell sums; the
  * parameters are those of logfx_extract_batch, smooth is ignored).  Every
  * cell must hold fewer than 2^32 pixels.  feats: DEVICE, n*3*128*128
- * bfloat16 values. */
+ * bfloat16 values.  With p->gate_region > 0 (n = 1, smooth =
+ * LOGFX_SMOOTH_GATE): one feature set per region, regions row-major, so
+ * regions*3*128*128 values. */
 int logfx_gate_features(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,
                         uint16_t *feats, void *stream);
 
@@ -331,7 +352,9 @@ int logfx_gate_step(logfx_ctx *ctx, const float *grad, double lr, void *stream);
 
 /* The gate on n images: features, network, decision.  logits: DEVICE
  * float[n] or NULL; decisions: DEVICE uint8[n] (1 = smooth) or NULL.
- * Needs gate parameters (LOGFX_EINVAL otherwise). */
+ * Needs gate parameters (LOGFX_EINVAL otherwise).  With p->gate_region > 0
+ * (n = 1): one logit and decision per region, regions row-major: the
+ * decisions logfx_extract takes with the same parameters. */
 int logfx_gate(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p, float *logits,
                uint8_t *decisions, void *stream);
 

@@ -34,7 +34,8 @@ constexpr int kOffBf = kOffWf + kC3;
 constexpr int kNParam = kOffBf + 1;          // 14369
 
 // Per-cell sums that pass 1 accumulates for every image (feature mode):
-// [image][2][kCellCount] of
+// [image][2][kCellCount] (or [2][gy kCells][gx kCells] for one image whose
+// gx x gy regions the gate decides one by one) of
 //   plane 0: sum of pixel values,
 //   plane 1: (pixels with Z_1 != 0) + 2^32 * (pixels with Z_2 != 0).
 // Plane 1 needs every cell to hold fewer than 2^32 pixels (checked on the host).
@@ -76,10 +77,11 @@ struct AdamArgs {
 };
 
 // Launchers (logfx_gate.hip).  They return hipSuccess or the launch error.
-hipError_t launch_zero_cells(unsigned long long *cells, int nimg, hipStream_t s);
-// Features of the images of a launch: bf16 [nimg][3][128][128] from the cell sums.
+hipError_t launch_zero_cells(unsigned long long *cells, long long nsets, hipStream_t s);
+// Features of the images of a launch: bf16 [nimg][gy gx][3][128][128] from
+// the cell sums (gx x gy regions per image, 1 x 1 for whole images).
 hipError_t launch_finish_features(const Launch &L, const unsigned long long *cells, double maxval,
-                                  uint16_t *feats, hipStream_t s);
+                                  uint16_t *feats, int gx, int gy, hipStream_t s);
 hipError_t launch_forward(const NetBuffers &n, hipStream_t s);
 hipError_t launch_backward(const NetBuffers &n, hipStream_t s);   // after launch_forward
 hipError_t launch_adamw(const AdamArgs &a, hipStream_t s);

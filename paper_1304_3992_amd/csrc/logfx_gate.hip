@@ -288,29 +288,38 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const float *src, uint16_t
 }
 
 // ---------------------------------------------------------------- features
-// Number of positions i in [0, n) with floor(i * kCells / n) == c.
-__device__ inline long long cell_span(long long c, long long n) {
-    return ((c + 1) * n + kCells - 1) / kCells - (c * n + kCells - 1) / kCells;
+// Number of positions i in [0, n) with floor(i * cells / n) == c.
+__device__ inline long long cell_span(long long c, long long n, long long cells) {
+    return ((c + 1) * n + cells - 1) / cells - (c * n + cells - 1) / cells;
 }
 
-// Cell sums of every image of a launch to bfloat16 features:
-// (mean value) / maxval, (pixels with Z_1 != 0) / area, (Z_2 != 0) / area.
+// Cell sums to bfloat16 features: (mean value) / maxval, (pixels with
+// Z_1 != 0) / area, (Z_2 != 0) / area.  Feature set blockIdx.y covers
+// image blockIdx.y / (gx gy) and, within it, region blockIdx.y % (gx gy)
+// (row-major, gx regions per row) of kCells x kCells cells; the image's
+// cell grid is gy kCells rows by gx kCells columns (gx = gy = 1: the whole
+// image).
 __global__ __launch_bounds__(256) void finish_features(Launch L, const unsigned long long *__restrict__ cells,
-                                                       double maxval, uint16_t *__restrict__ feats) {
-    const int img = blockIdx.y;
+                                                       double maxval, uint16_t *__restrict__ feats, int gx,
+                                                       int gy) {
+    const int set = blockIdx.y, nreg = gx * gy;
+    const int img = set / nreg, reg = set - img * nreg;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kCellCount) return;
     const ImageJob &J = L.nimg == 1 ? L.one : L.jobs[img];
-    const long long area = cell_span(i / kCells, J.img.H) * cell_span(i % kCells, J.img.W);
-    const unsigned long long *cs = cells + (long long)img * 2 * kCellCount;
-    uint16_t *f = feats + (long long)img * kFeatC * kCellCount;
+    const long long CX = (long long)gx * kCells, CY = (long long)gy * kCells;
+    const long long cy = (long long)(reg / gx) * kCells + i / kCells;
+    const long long cx = (long long)(reg % gx) * kCells + i % kCells;
+    const long long area = cell_span(cy, J.img.H, CY) * cell_span(cx, J.img.W, CX);
+    const unsigned long long *cs = cells + (long long)img * 2 * CX * CY + cy * CX + cx;
+    uint16_t *f = feats + (long long)set * kFeatC * kCellCount;
     if (area <= 0) {
         f[i] = f[kCellCount + i] = f[2 * kCellCount + i] = 0;
         return;
     }
     const double ar = (double)area;
-    const unsigned long long zz = cs[kCellCount + i];
-    f[i] = to_bf16((float)(((double)cs[i] / ar) / maxval));
+    const unsigned long long zz = cs[CX * CY];
+    f[i] = to_bf16((float)(((double)cs[0] / ar) / maxval));
     f[kCellCount + i] = to_bf16((float)((double)(zz & 0xFFFFFFFFull) / ar));
     f[2 * kCellCount + i] = to_bf16((float)((double)(zz >> 32) / ar));
 }
@@ -369,16 +378,16 @@ long long partial_elems(int B) {
     return (long long)B * (a > b ? (a > c ? a : c) : (b > c ? b : c));
 }
 
-hipError_t launch_zero_cells(unsigned long long *cells, int nimg, hipStream_t s) {
-    const long long n = (long long)nimg * 2 * kCellCount;
+hipError_t launch_zero_cells(unsigned long long *cells, long long nsets, hipStream_t s) {
+    const long long n = nsets * 2 * kCellCount;
     hipLaunchKernelGGL(zero_u64, dim3(blocks(n, 256)), dim3(256), 0, s, cells, n);
     return hipGetLastError();
 }
 
 hipError_t launch_finish_features(const Launch &L, const unsigned long long *cells, double maxval, uint16_t *feats,
-                                  hipStream_t s) {
-    hipLaunchKernelGGL(finish_features, dim3(blocks(kCellCount, 256), L.nimg), dim3(256), 0, s, L, cells, maxval,
-                       feats);
+                                  int gx, int gy, hipStream_t s) {
+    hipLaunchKernelGGL(finish_features, dim3(blocks(kCellCount, 256), L.nimg * gx * gy), dim3(256), 0, s, L, cells,
+                       maxval, feats, gx, gy);
     return hipGetLastError();
 }
 

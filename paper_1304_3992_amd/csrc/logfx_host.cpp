@@ -365,6 +365,9 @@ struct Plan {
     bool inexact = false; // the FP64 LoG sums round (LOGFX_ALLOW_INEXACT)
     int ncas = 0;         // further median levels (applied where the first level is)
     int cas[3] = {0, 0, 0};
+    int region = 0;       // > 0: the gate decides per region x region square (single images)
+    int gx = 1, gy = 1;   // regions per row / per column (powers of two)
+    int lgx = 0, lgy = 0; // their log2
 };
 
 int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Plan &pl) {
@@ -425,6 +428,32 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     pl.ra = std::max(1, std::min(r0, r1));
     pl.rb = std::max(1, std::max(r0, r1));
     pl.std5 = p->std5_max >= 0.0;
+    if (p->gate_region < 0) return set_err(ctx, LOGFX_EINVAL, "gate_region %d < 0", p->gate_region);
+    pl.region = 0;
+    pl.gx = pl.gy = 1;
+    pl.lgx = pl.lgy = 0;
+    if (p->gate_region > 0) {
+        const long long R = p->gate_region;
+        if (p->smooth != LOGFX_SMOOTH_GATE)
+            return set_err(ctx, LOGFX_EINVAL, "gate_region needs smooth = LOGFX_SMOOTH_GATE");
+        if (p->median_cascade[0] != 0)
+            return set_err(ctx, LOGFX_EINVAL, "gate_region and median_cascade cannot be combined");
+        if (R < 128 || R >= (1 << 23))
+            return set_err(ctx, LOGFX_EINVAL, "gate_region %lld not in 128 .. 2^23 - 1", R);
+        if (img->height % R != 0 || img->width % R != 0)
+            return set_err(ctx, LOGFX_EINVAL, "a %lld x %lld image is not a whole number of %lld-pixel regions",
+                           (long long)img->height, (long long)img->width, R);
+        const long long gx = img->width / R, gy = img->height / R;
+        if ((gx & (gx - 1)) != 0 || (gy & (gy - 1)) != 0)
+            return set_err(ctx, LOGFX_EINVAL, "%lld x %lld regions: both counts must be powers of two", gy, gx);
+        if (gx * gy > LOGFX_GATE_MAX_BATCH)
+            return set_err(ctx, LOGFX_EINVAL, "%lld regions: at most %d", gx * gy, LOGFX_GATE_MAX_BATCH);
+        pl.region = (int)R;
+        pl.gx = (int)gx;
+        pl.gy = (int)gy;
+        while ((1LL << pl.lgx) < gx) ++pl.lgx;
+        while ((1LL << pl.lgy) < gy) ++pl.lgy;
+    }
     pl.ncas = 0;
     if (p->smooth != LOGFX_SMOOTH_NEVER)
         while (pl.ncas < 3 && p->median_cascade[pl.ncas] != 0) {
@@ -521,19 +550,22 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
     if (n < 1 || !imgs) return set_err(ctx, LOGFX_EINVAL, "no images");
     int rc = check_all(ctx, &imgs[0], p, c.pl);
     if (rc != LOGFX_OK) return rc;
+    if (n > 1 && c.pl.region > 0) return set_err(ctx, LOGFX_EINVAL, "gate_region applies to single-image calls");
     // strengths are stored between the passes when the context allows it and
     // the memory for them can be had; the 5x5 first stage and the median
     // cascade are built on the stored strengths only, so they always ask
-    // for them (and the cascade for a byte per pixel between its levels)
+    // for them (and the cascade for a byte per pixel between its levels);
+    // so is the per-region gate
     c.storez = false;
-    const bool need_z = c.pl.std5 || c.pl.ncas > 0;
+    const bool need_z = c.pl.std5 || c.pl.ncas > 0 || c.pl.region > 0;
     if (need_out && (ctx->store_z || need_z)) {
         long long px = 0;
         for (int i = 0; i < n; ++i) px += (long long)imgs[i].height * imgs[i].width;
         c.storez = ensure_zmap(ctx, px, c.pl.path);
         if (!c.storez && need_z)
-            return set_err(ctx, LOGFX_ENOMEM, "the 5x5 first deviation stage and the median cascade need "
-                                              "%lld bytes of device memory for the crossing strengths",
+            return set_err(ctx, LOGFX_ENOMEM, "the 5x5 first deviation stage, the median cascade and the "
+                                              "per-region gate need %lld bytes of device memory for the "
+                                              "crossing strengths",
                            px * (c.pl.path == LOGFX_PATH_INT32 ? 8 : 16));
         if (c.pl.ncas > 0 && px > ctx->ccap) {
             (void)hipFree(ctx->cmap);
@@ -657,6 +689,8 @@ struct Launches {
     gate::NetBuffers net;
     int *flags;
     uint8_t *decisions;            // optional copy of the decisions (logfx_gate)
+    int nsets;                     // feature sets / decisions: images x regions
+    int gx, gy;                    // regions per image row / column (1, 1: whole images)
 };
 
 // How far a call runs.
@@ -692,6 +726,8 @@ void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *con
         a2.zmap = ctx->zmap;
     }
     a2.median_size = p->median_size;
+    a1.cells_lx = kGateCellsLog2 + c.pl.lgx;
+    a1.cells_ly = kGateCellsLog2 + c.pl.lgy;
     a2.std5 = c.pl.std5 && c.storez;
     for (int slot = 0; slot < 2; ++slot) {
         const double t = a2.std5 ? p->std5_max / c.pl.mi[c.pl.order[slot]].unit : 0.0;
@@ -703,22 +739,22 @@ hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int unti
     hipError_t e;
     const bool i32 = k.path == LOGFX_PATH_INT32;
     const int mode = (k.dbg ? kP1Maps : 0) | (k.features ? kP1Cells : 0) | (k.storez ? kP1StoreZ : 0);
-    if (k.features && (e = gate::launch_zero_cells(k.cells, k.fin.L.nimg, s)) != hipSuccess) return e;
+    if (k.features && (e = gate::launch_zero_cells(k.cells, k.nsets, s)) != hipSuccess) return e;
     e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, mode, k.grid1, s)
             : launch_pass1_d(k.ra, k.rb, k.p1.d, mode, k.grid1, s);
     if (e != hipSuccess || until == UNTIL_PASS1) return e;
     if (until < UNTIL_OUTPUT) {   // the gate alone: no thresholds needed
-        if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, s)) != hipSuccess) return e;
+        if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, k.gx, k.gy, s)) != hipSuccess) return e;
         if (until == UNTIL_FEATURES) return hipSuccess;
         if ((e = gate::launch_forward(k.net, s)) != hipSuccess) return e;
-        return gate::launch_decide(k.net.logits, k.flags, k.decisions, k.fin.L.nimg, s);
+        return gate::launch_decide(k.net.logits, k.flags, k.decisions, k.nsets, s);
     }
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if ((e = launch_finalize(k.fin, s)) != hipSuccess) return e;
     if (k.gated) {
-        if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, s)) != hipSuccess ||
+        if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, k.gx, k.gy, s)) != hipSuccess ||
             (e = gate::launch_forward(k.net, s)) != hipSuccess ||
-            (e = gate::launch_decide(k.net.logits, k.flags, k.decisions, k.fin.L.nimg, s)) != hipSuccess)
+            (e = gate::launch_decide(k.net.logits, k.flags, k.decisions, k.nsets, s)) != hipSuccess)
             return e;
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -732,10 +768,10 @@ hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int unti
 }
 
 // Every cell of the gate's feature grid must hold fewer than 2^32 pixels.
-int check_cells(logfx_ctx *ctx, int n, const logfx_image *imgs) {
+int check_cells(logfx_ctx *ctx, int n, const logfx_image *imgs, const Plan &pl) {
     for (int i = 0; i < n; ++i) {
-        const long long ch = (imgs[i].height + gate::kCells - 1) / gate::kCells;
-        const long long cw = (imgs[i].width + gate::kCells - 1) / gate::kCells;
+        const long long ch = (imgs[i].height / pl.gy + gate::kCells - 1) / gate::kCells;
+        const long long cw = (imgs[i].width / pl.gx + gate::kCells - 1) / gate::kCells;
         if (ch * cw >= (1LL << 32))
             return set_err(ctx, LOGFX_EUNSUPPORTED, "image %d: gate cells of more than 2^32 pixels", i);
     }
@@ -755,10 +791,13 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
     k.storez = c.storez;
     if (k.path == LOGFX_PATH_INT32) fill_args<OrbitTapsI, int>(c, ctx, p, L, Z, k.p1.i, k.p2.i, k.dbg);
     else fill_args<OrbitTapsD, double>(c, ctx, p, L, Z, k.p1.d, k.p2.d, k.dbg);
+    k.gx = c.pl.gx;
+    k.gy = c.pl.gy;
+    k.nsets = c.n * c.pl.gx * c.pl.gy;
     if (gate > 0) {
         auto &G = ctx->gate;
         int rc;
-        if ((rc = ensure_gate_images(ctx, c.n)) != LOGFX_OK) return rc;
+        if ((rc = ensure_gate_images(ctx, k.nsets)) != LOGFX_OK) return rc;
         k.features = true;
         k.cells = G.cells;
         k.feats = feats ? feats : G.feats;
@@ -766,12 +805,19 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
         if (k.path == LOGFX_PATH_INT32) k.p1.i.cells = G.cells;
         else k.p1.d.cells = G.cells;
         if (gate > 1) {
-            if ((rc = ensure_gate_batch(ctx, c.n)) != LOGFX_OK) return rc;
+            if ((rc = ensure_gate_batch(ctx, k.nsets)) != LOGFX_OK) return rc;
             k.gated = true;
-            k.net = net_buffers(ctx, c.n, k.feats, nullptr, nullptr, nullptr, nullptr);
+            k.net = net_buffers(ctx, k.nsets, k.feats, nullptr, nullptr, nullptr, nullptr);
             k.flags = G.flags;
-            if (k.path == LOGFX_PATH_INT32) k.p2.i.med_flags = G.flags;
-            else k.p2.d.med_flags = G.flags;
+            if (k.path == LOGFX_PATH_INT32) {
+                k.p2.i.med_flags = G.flags;
+                k.p2.i.region = c.pl.region;
+                k.p2.i.reg_gx = c.pl.gx;
+            } else {
+                k.p2.d.med_flags = G.flags;
+                k.p2.d.region = c.pl.region;
+                k.p2.d.reg_gx = c.pl.gx;
+            }
         }
     }
     k.halo2 = c.pl.std5 ? kHalo2Z5 : kHalo2Z;
@@ -863,12 +909,12 @@ int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, const Lau
     auto &G = ctx->gate;
     hipError_t e;
     if (k.gated) {
-        if ((rc = grow_host(ctx, G.h_logits, G.h_cap, c.n)) != LOGFX_OK ||
-            (rc = grow_host(ctx, G.h_flags, G.h_capf, c.n)) != LOGFX_OK)
+        if ((rc = grow_host(ctx, G.h_logits, G.h_cap, k.nsets)) != LOGFX_OK ||
+            (rc = grow_host(ctx, G.h_flags, G.h_capf, k.nsets)) != LOGFX_OK)
             return rc;
-        if ((e = hipMemcpyAsync(G.h_logits, k.net.logits, sizeof(float) * c.n, hipMemcpyDeviceToHost, s)) !=
+        if ((e = hipMemcpyAsync(G.h_logits, k.net.logits, sizeof(float) * k.nsets, hipMemcpyDeviceToHost, s)) !=
                 hipSuccess ||
-            (e = hipMemcpyAsync(G.h_flags, k.flags, sizeof(int) * c.n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            (e = hipMemcpyAsync(G.h_flags, k.flags, sizeof(int) * k.nsets, hipMemcpyDeviceToHost, s)) != hipSuccess)
             return hip_err(ctx, e, "report copy");
     }
     if ((e = hipMemcpyAsync(ctx->h_stats, ctx->stats, sizeof(DevStats) * c.n, hipMemcpyDeviceToHost, s)) !=
@@ -898,7 +944,12 @@ int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, const Lau
         r.path = c.pl.path;
         r.inexact = c.pl.inexact ? 1 : 0;
         r.smoothed = p->smooth != LOGFX_SMOOTH_NEVER;
-        if (k.gated) {
+        if (k.gated && c.pl.region > 0) {   // one image: the flags of its regions
+            r.gated = 1;
+            r.regions = k.nsets;
+            for (int q = 0; q < k.nsets; ++q) r.regions_smoothed += G.h_flags[q] != 0;
+            r.smoothed = r.regions_smoothed > 0;
+        } else if (k.gated) {
             r.gated = 1;
             r.smoothed = G.h_flags[i] != 0;
             r.gate_logit = G.h_logits[i];
@@ -921,7 +972,7 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
     int rc = prepare(ctx, n, imgs, p, outs, !maps, c, s);
     if (rc != LOGFX_OK) return rc;
     const bool gated = !maps && p->smooth == LOGFX_SMOOTH_GATE && ctx->gate.loaded;
-    if (gated && (rc = check_cells(ctx, n, imgs)) != LOGFX_OK) return rc;
+    if (gated && (rc = check_cells(ctx, n, imgs, c.pl)) != LOGFX_OK) return rc;
     Launches k;
     if ((rc = build_launches(ctx, c, p, maps_L, maps_Z, k, gated ? 2 : 0)) != LOGFX_OK) return rc;
     hipError_t e;
@@ -962,14 +1013,14 @@ int run_gate(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params 
     Call c;
     int rc = prepare(ctx, n, imgs, p, nullptr, false, c, s);
     if (rc != LOGFX_OK) return rc;
-    if ((rc = check_cells(ctx, n, imgs)) != LOGFX_OK) return rc;
+    if ((rc = check_cells(ctx, n, imgs, c.pl)) != LOGFX_OK) return rc;
     Launches k;
     if ((rc = build_launches(ctx, c, p, nullptr, nullptr, k, until == UNTIL_FEATURES ? 1 : 2, feats)) != LOGFX_OK)
         return rc;
     k.decisions = decisions;
     hipError_t e;
     if ((e = launch_all(k, s, nullptr, until)) != hipSuccess) return hip_err(ctx, e, "kernel launch");
-    if (logits && (e = hipMemcpyAsync(logits, k.net.logits, sizeof(float) * n, hipMemcpyDeviceToDevice, s)) !=
+    if (logits && (e = hipMemcpyAsync(logits, k.net.logits, sizeof(float) * k.nsets, hipMemcpyDeviceToDevice, s)) !=
                       hipSuccess)
         return hip_err(ctx, e, "logit copy");
     return LOGFX_OK;

@@ -110,10 +110,14 @@ struct Pass1Args {
     // Strength pairs (kP1StoreZ): int2 (integer path) or double2 (FP64
     // path) per pixel, image i at element jobs[i].zoff, row pitch W.
     void *zmap;
-    // Gate features (kP1Cells): [nimg][2][kGateCells^2] counters, zeroed
-    // before the launch; plane 0 sums pixel values, plane 1 sums
+    // Gate features (kP1Cells): [nimg][2][cells] counters, zeroed before
+    // the launch; plane 0 sums pixel values, plane 1 sums
     // [Z_1 != 0] + 2^32 [Z_2 != 0] (every cell must hold < 2^32 pixels).
+    // Each image is cut into 2^cells_ly rows by 2^cells_lx columns of cells
+    // (kGateCells x kGateCells, or that grid per region when the gate
+    // decides per region of a single image).
     unsigned long long *cells;
+    int cells_lx, cells_ly;
 };
 
 template <class Taps>
@@ -133,6 +137,8 @@ struct Pass2Args {
     double thr600[2];       // 600 (std5_max / unit_j)^2, compared with 25 sum z^2 - (sum z)^2
     uint8_t *out_map;       // or nullptr: output of image i at out_map + jobs[i].zoff, pitch W
                             // (the first level of a median cascade; stored strengths only)
+    int region;             // > 0 (single image, gated): med_flags holds one flag per square
+    int reg_gx;             // region of this side, reg_gx regions per region row, row-major
 };
 
 // One further level of the hybrid median cascade, on maps of 0/1 bytes,

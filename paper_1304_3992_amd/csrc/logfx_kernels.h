@@ -441,8 +441,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     const int t0 = g.y0 - HL;
     const uint16_t *lrow = lds + (2 * RB) * g.stride + g.lc;   // LDS row of step si
 
-    // Feature mode: the image is cut into kGateCells x kGateCells cells
-    // (row r and column x belong to cell (r * cells / H, x * cells / W)).
+    // Feature mode: the image is cut into CY x CX cells, CY = 2^cells_ly,
+    // CX = 2^cells_lx (row r and column x belong to cell (r * CY / H,
+    // x * CX / W)).
     // Each lane sums its pixel values and crossing indicators down its
     // column while the rows stay in one cell row.  At the end of a cell row
     // (or of the strip) -- a row boundary that every wave of the workgroup
@@ -458,13 +459,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     if constexpr ((MODE & kP1Cells) != 0) {
         // floor(n * cells / d) in FP64: exact, since n * cells < 2^53 and a
         // non-integer quotient lies at least 1/d from an integer
-        auto cell_of = [](long long n, long long d) { return (int)floor((double)n * kGateCells / (double)d); };
-        fkey0 = cell_of(g.x0, g.W);
-        fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, g.W) - fkey0 + 1;
-        fslot = g.outc ? cell_of(g.xc, g.W) - fkey0 : 0;
-        fcy = cell_of(g.y0, g.H);
-        fnext = (((long long)fcy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2;
-        fcells = a.cells + (long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) * 2 * kGateCells * kGateCells;
+        auto cell_of = [](long long n, int cells, long long d) { return (int)floor((double)n * cells / (double)d); };
+        const int CX = 1 << a.cells_lx, CY = 1 << a.cells_ly;
+        fkey0 = cell_of(g.x0, CX, g.W);
+        fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, CX, g.W) - fkey0 + 1;
+        fslot = g.outc ? cell_of(g.xc, CX, g.W) - fkey0 : 0;
+        fcy = cell_of(g.y0, CY, g.H);
+        fnext = (((long long)fcy + 1) * g.H + CY - 1) >> a.cells_ly;
+        fcells = a.cells + ((long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) << (a.cells_lx + a.cells_ly + 1));
     }
     auto flush = [&](const int r) __attribute__((always_inline)) {
         if (g.outc && (fv | fc)) {
@@ -475,9 +477,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         if ((int)threadIdx.x < fslots) {
             const unsigned v = cellv[threadIdx.x], c = cellc[threadIdx.x];
             if (v | c) {
-                unsigned long long *cell = fcells + (long long)fcy * kGateCells + fkey0 + threadIdx.x;
+                unsigned long long *cell = fcells + ((long long)fcy << a.cells_lx) + fkey0 + threadIdx.x;
                 atomicAdd(cell, (unsigned long long)v);
-                atomicAdd(cell + kGateCells * kGateCells,
+                atomicAdd(cell + (1ll << (a.cells_lx + a.cells_ly)),
                           (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
                 cellv[threadIdx.x] = cellc[threadIdx.x] = 0;
             }
@@ -487,9 +489,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         // the cell row of row r + 1 (cells may be empty when H < cells):
         // the first c > fcy whose rows reach past r, by shifts only
         int cy = fcy + 1;
-        while (((((long long)cy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2) <= r + 1) ++cy;
+        const long long CY = 1ll << a.cells_ly;
+        while (((((long long)cy + 1) * g.H + CY - 1) >> a.cells_ly) <= r + 1) ++cy;
         fcy = cy;
-        fnext = (((long long)cy + 1) * g.H + kGateCells - 1) >> kGateCellsLog2;
+        fnext = (((long long)cy + 1) * g.H + CY - 1) >> a.cells_ly;
     };
 
     // One step = one new input row.  Full groups of P steps are unrolled so

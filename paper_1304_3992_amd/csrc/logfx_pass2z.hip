@@ -98,6 +98,11 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         uint8_t *const obase = a.out_map ? a.out_map + J.zoff : J.out;
         const long long opitch = a.out_map ? (long long)W : J.out_pitch;
 
+        // gated per region: the region column of the lane's (clamped) column
+        int rx = 0;
+        if constexpr (MED < 0) {
+            if (a.region > 0) rx = min(max(xc, 0), W - 1) / a.region;
+        }
         const double thr600_0 = a.thr600[0], thr600_1 = a.thr600[1];
         double Zs[2][NR] = {}, Zq[2][NR] = {};   // 3x3 deviation row sums of the last NR rows read
         double Ws[2][NR] = {}, Wq[2][NR] = {};   // 5x5 deviation row sums (S5)
@@ -132,6 +137,20 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             unsigned f;
             if constexpr (M == 0) f = c;
             else f = median_word<M>(w0, w1);
+            if constexpr (MED < 0 && M != 0) {
+                if (a.region > 0) {
+                    // each pixel takes F or E as its region's flag says; the
+                    // word's rows cross at most one region boundary, at bit d
+                    const int R = a.region, yr = y0 + wb, ry = yr / R;
+                    const int d = (ry + 1) * R - yr;
+                    const unsigned nxt = d >= 32 ? 0u : ~0u << d;
+                    const int *fl = a.med_flags + (long long)ry * a.reg_gx + rx;
+                    const unsigned s0 = fl[0] ? ~0u : 0u;
+                    const unsigned s1 = (nxt != 0u && (ry + 1) * R < H) ? (fl[a.reg_gx] ? ~0u : 0u) : 0u;
+                    const unsigned sel = (s0 & ~nxt) | (s1 & nxt);
+                    f = (f & sel) | (c & ~sel);
+                }
+            }
             const unsigned rm = (n >= 32 ? ~0u : (1u << n) - 1u) & outm;
             ecnt += __popc(c & rm);
             fcnt += __popc(f & rm);
@@ -249,9 +268,9 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
     for_each_tile<LOOP>(a.L.total2, [&](const int item) __attribute__((always_inline)) {
         if constexpr (MED >= 0) {
             tile(item, int_c<MED>{});
-        } else {   // gated: the median of each image as its flag says
+        } else {   // gated: the median of each image (or region) as its flag says
             const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
-            if (a.med_flags[image]) tile(item, int_c<-MED>{});
+            if (a.region > 0 || a.med_flags[image]) tile(item, int_c<-MED>{});
             else tile(item, int_c<0>{});
         }
     });

@@ -53,7 +53,7 @@ class logfx_params(ctypes.Structure):
                 ("std_mode", ctypes.c_int32), ("std_k", ctypes.c_double),
                 ("std5_max", ctypes.c_double), ("smooth", ctypes.c_int32),
                 ("median_size", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("median_cascade", ctypes.c_int32 * 3)]
+                ("median_cascade", ctypes.c_int32 * 3), ("gate_region", ctypes.c_int32)]
 
 
 class logfx_tune_result(ctypes.Structure):
@@ -68,14 +68,16 @@ class logfx_report(ctypes.Structure):
                 ("extracted", ctypes.c_int64), ("output", ctypes.c_int64),
                 ("path", ctypes.c_int32), ("smoothed", ctypes.c_int32),
                 ("gated", ctypes.c_int32), ("gate_fallback", ctypes.c_int32),
-                ("gate_logit", ctypes.c_double), ("inexact", ctypes.c_int32)]
+                ("gate_logit", ctypes.c_double), ("inexact", ctypes.c_int32),
+                ("regions", ctypes.c_int32), ("regions_smoothed", ctypes.c_int32)]
 
     def as_dict(self):
         return {"pixels": self.pixels, "sigma_g": list(self.sigma_g), "thresh": list(self.thresh),
                 "zc_count": list(self.zc_count), "extracted": self.extracted,
                 "output": self.output, "path": self.path, "smoothed": self.smoothed,
                 "gated": self.gated, "gate_fallback": self.gate_fallback,
-                "gate_logit": self.gate_logit, "inexact": self.inexact}
+                "gate_logit": self.gate_logit, "inexact": self.inexact,
+                "regions": self.regions, "regions_smoothed": self.regions_smoothed}
 
 
 _lib = None
@@ -181,7 +183,7 @@ class Params:
     """Holds a logfx_params struct and keeps its tap arrays alive."""
 
     def __init__(self, taps1, taps2, *, zc_thresh=0.0, std_mode=STD_REL, std_k=2.0,
-                 std5_max=-1.0, smooth=True, median_size=5, flags=0, median_cascade=()):
+                 std5_max=-1.0, smooth=True, median_size=5, flags=0, median_cascade=(), gate_region=0):
         self.t1 = np.ascontiguousarray(taps1, dtype=np.float32)
         self.t2 = np.ascontiguousarray(taps2, dtype=np.float32)
         p = logfx_params()
@@ -201,7 +203,16 @@ class Params:
             raise ValueError("at most 3 further median levels")
         for i, m in enumerate(cas + [0] * (3 - len(cas))):
             p.median_cascade[i] = m
+        p.gate_region = gate_region
         self.c = p
+
+
+def _feature_sets(imgs, params: Params) -> int:
+    """Images, or regions of the single image when params.gate_region > 0."""
+    r = params.c.gate_region
+    if r > 0 and len(imgs) == 1 and imgs[0].shape[0] % r == 0 and imgs[0].shape[1] % r == 0:
+        return (imgs[0].shape[0] // r) * (imgs[0].shape[1] // r)
+    return len(imgs)   # the library rejects any other region geometry
 
 
 def _torch_dtype_code(t) -> int:
@@ -359,7 +370,8 @@ class Context:
         imgs, descs = self._descs(imgs, bits)
         n = len(imgs)
         if feats is None:
-            feats = torch.empty((n, 3, GATE_CELLS, GATE_CELLS), dtype=torch.bfloat16, device=imgs[0].device)
+            sets = _feature_sets(imgs, params)
+            feats = torch.empty((sets, 3, GATE_CELLS, GATE_CELLS), dtype=torch.bfloat16, device=imgs[0].device)
         rc = self.lib.logfx_gate_features(self.ptr, n, descs, ctypes.byref(params.c),
                                           ctypes.c_void_p(feats.data_ptr()), _stream_ptr(stream))
         _check(rc, self.ptr)
@@ -420,12 +432,14 @@ class Context:
         _check(self.lib.logfx_gate_step(self.ptr, gp, float(lr), _stream_ptr(stream)), self.ptr)
 
     def gate(self, imgs, params: Params, *, bits: int = 0, stream=None):
-        """logfx_gate: (logits float [n], decisions uint8 [n]) device tensors."""
+        """logfx_gate: (logits float [n], decisions uint8 [n]) device tensors
+        (one per region, row-major, when params.gate_region > 0)."""
         import torch
         imgs, descs = self._descs(imgs, bits)
         n = len(imgs)
-        logits = torch.empty(n, dtype=torch.float32, device=imgs[0].device)
-        dec = torch.empty(n, dtype=torch.uint8, device=imgs[0].device)
+        sets = _feature_sets(imgs, params)
+        logits = torch.empty(sets, dtype=torch.float32, device=imgs[0].device)
+        dec = torch.empty(sets, dtype=torch.uint8, device=imgs[0].device)
         rc = self.lib.logfx_gate(self.ptr, n, descs, ctypes.byref(params.c),
                                  ctypes.c_void_p(logits.data_ptr()), ctypes.c_void_p(dec.data_ptr()),
                                  _stream_ptr(stream))

@@ -212,3 +212,25 @@ def test_allow_inexact_flag(lib):
     assert _rc(_img(), logfx.Params(m1, m2, flags=logfx.ALLOW_INEXACT)) == (logfx.OK, logfx.PATH_FP64)
     # exact masks are unaffected by the flag
     assert _rc(_img(), _params(flags=logfx.ALLOW_INEXACT)) == (logfx.OK, logfx.PATH_INT32)
+
+
+def test_gate_region_checks(lib):
+    """The per-region gate: square regions that tile the image exactly, a
+    power-of-two count of them each way, GATE smoothing, no cascade."""
+    g = logfx.SMOOTH_GATE
+    ok = (logfx.OK, logfx.PATH_INT32)
+    assert _rc(_img(1024, 512), _params(smooth=g, gate_region=256)) == ok      # 4 x 2 regions
+    assert _rc(_img(128, 128), _params(smooth=g, gate_region=128)) == ok       # one region
+    assert _rc(_img(16, 16), _params(smooth=g, gate_region=0)) == ok           # off
+    bad = [
+        (_img(512, 512), dict(smooth=g, gate_region=-1)),                      # negative
+        (_img(512, 512), dict(smooth=True, gate_region=256)),                  # not GATE
+        (_img(512, 512), dict(smooth=g, gate_region=256, median_cascade=(3,))),
+        (_img(512, 512), dict(smooth=g, gate_region=64)),                      # below 128
+        (_img(512, 500), dict(smooth=g, gate_region=250)),                     # 512 % 250 != 0
+        (_img(768, 512), dict(smooth=g, gate_region=256)),                     # 3 regions down
+        (_img(520, 512), dict(smooth=g, gate_region=256)),                     # ragged
+        (_img(1 << 17, 1 << 17, pitch=1 << 17), dict(smooth=g, gate_region=128)),  # 2^20 regions
+    ]
+    rcs = [_rc(im, _params(**kw))[0] for im, kw in bad]
+    assert rcs == [logfx.EINVAL] * len(bad), rcs

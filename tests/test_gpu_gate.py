@@ -343,3 +343,76 @@ def test_gate_decides_the_median_cascade(ctx):
         torch.cuda.synchronize()
         for o, e in zip(outs, ref):
             assert torch.equal(o, e)
+
+
+def _region_scene(gy, gx, R, seed0):
+    """gy x gx gate tiles of side R, each with its own noise, side by side
+    in one image (the regions' seams are part of the scene)."""
+    rows = []
+    for y in range(gy):
+        rows.append(np.concatenate([scenes.gate_tile(seed0 + y * gx + x, size=R, twin=False)[0]
+                                    for x in range(gx)], axis=1))
+    return np.ascontiguousarray(np.concatenate(rows, axis=0))
+
+
+@pytest.mark.parametrize("gy,gx,R,median_size", [(2, 4, 256, 5), (4, 2, 128, 3), (1, 1, 384, 5)])
+def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
+    """gate_region: one image, one global deviation per mask, and a gate
+    decision per R x R region.  The features of each region are the oracle's
+    features of that region's part of the whole image's crossing maps (bit
+    for bit); the logits match the oracle network; the output is the
+    oracle's smoothed map F in the smoothed regions and its unsmoothed map E
+    elsewhere (band rule), with the median reading across region borders."""
+    import torch
+    from parity import compare
+    img = _region_scene(gy, gx, R, 20_000 + 97 * R)
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t, smooth=True, median_size=median_size)
+    regions = [(y, x) for y in range(gy) for x in range(gx)]
+    crop = lambda a, y, x: a[y * R:(y + 1) * R, x * R:(x + 1) * R]
+    feats_ref = np.stack([og.features(crop(img, y, x), crop(o["Z1"], y, x), crop(o["Z2"], y, x), 11)
+                          for y, x in regions])
+    theta = og.init(103)
+    theta[og.NPARAM - 1] = 0.0
+    z0, _ = og.forward(theta, feats_ref)
+    # the output bias splits the regions between both choices, well away from 0
+    zs = np.sort(z0)
+    k = len(zs) // 2
+    theta[og.NPARAM - 1] = -float(zs[k - 1] + zs[k]) / 2 if len(zs) > 1 else 1.0
+    z_ref, _ = og.forward(theta, feats_ref)
+    ctx.gate_set_params(theta)
+    params = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, median_size=median_size, gate_region=R)
+    dev = to_device(img)
+    feats = ctx.gate_features(dev, params, bits=11)
+    logits, dec = ctx.gate(dev, params, bits=11)
+    out, rep = ctx.extract(dev, params, bits=11, report=True)
+    torch.cuda.synchronize()
+    got = feats.float().cpu().numpy().astype(np.float64)
+    assert got.shape == (len(regions), 3, 128, 128)
+    assert np.array_equal(got, og.bf16(feats_ref))
+    logits = logits.cpu().numpy()
+    dec = dec.cpu().numpy()
+    assert np.all(np.abs(logits - z_ref) <= LOGIT_TOL * (1 + np.abs(z_ref))), (logits, z_ref)
+    sure = np.abs(z_ref) > LOGIT_TOL
+    assert np.array_equal(dec[sure], (z_ref[sure] > 0).astype(np.uint8))
+    if len(regions) > 1:
+        assert 0 < dec.sum() < len(regions)
+    assert rep["gated"] == 1 and rep["gate_fallback"] == 0
+    assert rep["regions"] == len(regions) and rep["regions_smoothed"] == int(dec.sum())
+    assert rep["sigma_g"] == pytest.approx(list(o["stats"][:2]), rel=1e-12)
+    ref = o["E"].copy()
+    for q, (y, x) in enumerate(regions):
+        if dec[q]:
+            ref[y * R:(y + 1) * R, x * R:(x + 1) * R] = crop(o["F"], y, x)
+    compare(out.cpu().numpy(), {**o, "F": ref}, smooth=True, median_size=median_size)
+
+
+def test_gate_regions_refused_in_batches(ctx):
+    """gate_region belongs to single-image calls."""
+    _, lib_t = masks()
+    ctx.gate_set_params(og.init(5))
+    img = to_device(np.zeros((256, 256), np.uint16))
+    params = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, gate_region=128)
+    with pytest.raises(logfx.LogfxError) as e:
+        ctx.extract_batch([img, img], params, bits=11)
+    assert e.value.code == logfx.EINVAL
