@@ -221,3 +221,22 @@ def config5_index(size: int = 16384, tile: int = 2048, bands: int = 4):
     """(band, ty, tx) of every tile, in order."""
     n = size // tile
     return [(b, ty, tx) for b in range(bands) for ty in range(n) for tx in range(n)]
+
+
+def regional_noise_scene(height: int = 4096, width: int = 16384, region: int = 2048, seed: int = 6,
+                         bits: int = 11) -> np.ndarray:
+    """A noise-free 11-bit scene at the 8192^2 generator's density of
+    rectangles and polylines, then each region x region square with its own
+    Gaussian noise sigma ~ U[0, 20] and salt-and-pepper density ~ U[0, 0.2]
+    (the four-band workload's noise law, on one seamless image)."""
+    area = height * width / (8192.0 * 8192.0)
+    base = panchromatic(height, width, seed, n_rect=int(20000 * area), n_poly=int(500 * area),
+                        noise_sigma=0.0, sp_density=0.0, bits=bits).astype(np.float64)
+    rng = np.random.default_rng(seed + 1)
+    maxv = (1 << bits) - 1
+    out = np.empty((height, width), np.uint16)
+    for y in range(0, height, region):
+        for x in range(0, width, region):
+            sigma, density = float(rng.uniform(0.0, 20.0)), float(rng.uniform(0.0, 0.2))
+            out[y:y + region, x:x + region] = _noise(base[y:y + region, x:x + region], rng, sigma, density, maxv)
+    return out

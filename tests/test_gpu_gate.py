@@ -416,3 +416,43 @@ def test_gate_regions_refused_in_batches(ctx):
     with pytest.raises(logfx.LogfxError) as e:
         ctx.extract_batch([img, img], params, bits=11)
     assert e.value.code == logfx.EINVAL
+
+
+def test_gate_regions_full_width_band(ctx):
+    """The seamless mode at the four-band workload's shape: a 4096 x 16384
+    strip of a band (16384 columns, 2048^2 regions, 2 x 8 of them) with its
+    own noise per region, the committed gate parameters, and the launch
+    configuration the benchmark times.  Decisions follow the oracle network
+    on the oracle's region features (outside |logit| < tolerance); the output
+    is F or E per region under the band rule."""
+    import torch
+    from parity import compare
+    R = 2048
+    img = scenes.regional_noise_scene(4096, 16384, R, seed=6)
+    orc_t, lib_t = masks()
+    o = run_oracle(img, orc_t, smooth=True)
+    gy, gx = img.shape[0] // R, img.shape[1] // R
+    regions = [(y, x) for y in range(gy) for x in range(gx)]
+    crop = lambda a, y, x: a[y * R:(y + 1) * R, x * R:(x + 1) * R]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ctx.gate_load(os.path.join(root, "paper_1304_3992_amd", "gate_weights.bin"))
+    theta = ctx.gate_get_params().astype(np.float64)
+    feats_ref = np.stack([og.features(crop(img, y, x), crop(o["Z1"], y, x), crop(o["Z2"], y, x), 11)
+                          for y, x in regions])
+    z_ref, _ = og.forward(theta, feats_ref)
+    params = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, gate_region=R)
+    dev = to_device(img)
+    out, rep = ctx.extract(dev, params, bits=11, report=True)
+    logits, dec = ctx.gate(dev, params, bits=11)
+    torch.cuda.synchronize()
+    logits, dec = logits.cpu().numpy(), dec.cpu().numpy()
+    assert np.all(np.abs(logits - z_ref) <= LOGIT_TOL * (1 + np.abs(z_ref))), (logits, z_ref)
+    sure = np.abs(z_ref) > LOGIT_TOL
+    assert np.array_equal(dec[sure], (z_ref[sure] > 0).astype(np.uint8))
+    assert rep["regions"] == len(regions) and rep["regions_smoothed"] == int(dec.sum())
+    ref = o["E"].copy()
+    for q, (y, x) in enumerate(regions):
+        if dec[q]:
+            ref[y * R:(y + 1) * R, x * R:(x + 1) * R] = crop(o["F"], y, x)
+    info = compare(out.cpu().numpy(), {**o, "F": ref}, smooth=True)
+    print("full-width band:", int(dec.sum()), "of", len(regions), "regions smoothed;", info)
