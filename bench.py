@@ -62,7 +62,7 @@ PASS2Z_OPS_PER_PX = 2 * 12 + 3
 # (scaled by a plain copy of known size; profiles/pipeline_kernels_8192x8192_u16.md)
 # for the kernel sources with this hash.  Reported only while the sources are
 # unchanged.
-TRAFFIC_SOURCE_HASH = "a136838613b9d0bb"
+TRAFFIC_SOURCE_HASH = "f965f10e4e0916f2"
 TRAFFIC_BYTES = {"pass1_kernel": (68995 * 2.0 + 525282 * 1.0) * 1024,
                  "pass2z_kernel": (296685 * 2.0 + 81738 * 1.0) * 1024}
 # Algorithmic HBM bytes per pixel of each kernel: pass 1 reads the 16-bit
@@ -162,6 +162,10 @@ def bench_gated(args):
     stream = torch.cuda.current_stream()
     res = {}
     decisions = None
+    if not args.no_tune:   # strip heights for the batch, shared by its three modes
+        tuned = ctx.tune(devs, logfx.Params(*lib_taps, smooth=logfx.SMOOTH_GATE), outs, bits=11, reps=3)
+        res["tuned_batch"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"], "persistent": tuned["persistent"]}
+        log(f"batch tuned: rows {tuned['rows1']}/{tuned['rows2']}, persistent {tuned['persistent']}")
     for name, mode in modes.items():
         params = logfx.Params(*lib_taps, smooth=mode)
         _, reps = ctx.extract_batch(devs, params, outs, bits=11, report=True)
@@ -205,6 +209,10 @@ def bench_gated(args):
     del devs
     bouts = [torch.empty(t.shape, dtype=torch.uint8, device="cuda") for t in bands]
     params = logfx.Params(*lib_taps, smooth=logfx.SMOOTH_GATE, gate_region=T)
+    if not args.no_tune:
+        tuned = ctx.tune(bands[0], params, [bouts[0]], bits=11, reps=3)
+        res["tuned_seamless"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"]}
+        log(f"seamless tuned: rows {tuned['rows1']}/{tuned['rows2']}")
     seam_dec = []
     for bt, bo in zip(bands, bouts):
         _, rep = ctx.extract(bt, params, bo, bits=11, report=True)

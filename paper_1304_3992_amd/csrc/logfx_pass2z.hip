@@ -77,7 +77,9 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
     constexpr int NR = 2 * WR + 1;        // rows of row sums kept
     constexpr int G = S5 ? 5 : 6;         // rows read ahead of their use (a multiple of the ring)
 
-    auto tile = [&](const int item, auto medc) __attribute__((always_inline)) {
+    // mixed: (gated per region) the tile's output pixels span regions, so
+    // each pixel takes F or E by its own region's flag
+    auto tile = [&](const int item, auto medc, const bool mixed) __attribute__((always_inline)) {
         constexpr int M = decltype(medc)::value;
         const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
         const ImageJob J = job_of(a.L, image);
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
         // gated per region: the region column of the lane's (clamped) column
         int rx = 0;
         if constexpr (MED < 0) {
-            if (a.region > 0) rx = min(max(xc, 0), W - 1) / a.region;
+            if (mixed) rx = min(max(xc, 0), W - 1) / a.region;
         }
         const double thr600_0 = a.thr600[0], thr600_1 = a.thr600[1];
         double Zs[2][NR] = {}, Zq[2][NR] = {};   // 3x3 deviation row sums of the last NR rows read
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             if constexpr (M == 0) f = c;
             else f = median_word<M>(w0, w1);
             if constexpr (MED < 0 && M != 0) {
-                if (a.region > 0) {
+                if (mixed) {
                     // each pixel takes F or E as its region's flag says; the
                     // word's rows cross at most one region boundary, at bit d
                     const int R = a.region, yr = y0 + wb, ry = yr / R;
@@ -267,11 +269,25 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
     };
     for_each_tile<LOOP>(a.L.total2, [&](const int item) __attribute__((always_inline)) {
         if constexpr (MED >= 0) {
-            tile(item, int_c<MED>{});
+            tile(item, int_c<MED>{}, false);
         } else {   // gated: the median of each image (or region) as its flag says
             const int image = a.L.nimg == 1 ? 0 : a.L.owner2[item];
-            if (a.region > 0 || a.med_flags[image]) tile(item, int_c<-MED>{});
-            else tile(item, int_c<0>{});
+            int flag;
+            bool mixed = false;
+            if (a.region > 0) {
+                // a tile inside one region takes that region's flag as a whole
+                const ImageJob J = job_of(a.L, image);
+                const int t = item - J.base2, tx = t % J.tiles_x2, ty = t / J.tiles_x2;
+                const int x0 = tx * TW, y0 = ty * a.rows;
+                const int x1 = min(x0 + TW, (int)J.img.W) - 1, y1 = min(y0 + a.rows, (int)J.img.H) - 1;
+                const int R = a.region;
+                mixed = x0 / R != x1 / R || y0 / R != y1 / R;
+                flag = a.med_flags[(y0 / R) * a.reg_gx + x0 / R];
+            } else {
+                flag = a.med_flags[image];
+            }
+            if (mixed || flag) tile(item, int_c<-MED>{}, mixed);
+            else tile(item, int_c<0>{}, false);
         }
     });
 }
