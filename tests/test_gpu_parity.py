@@ -182,6 +182,17 @@ def test_config2_full_size(ctx):
     info = compare(F, o, smooth=True)
     assert rep["path"] == logfx.PATH_INT32
     np.testing.assert_allclose(rep["sigma_g"], o["stats"][:2], rtol=1e-12)
+    # the benchmark's own launch: strip heights chosen by the tuner
+    opts = (logfx.OPT_ROWS1, logfx.OPT_ROWS2, logfx.OPT_PERSISTENT)
+    saved = [ctx.get_option(k) for k in opts]
+    try:
+        ctx.tune(to_device(img), logfx.Params(*lib_t), bits=11, reps=3)
+        Ft, _ = run_gpu(ctx, img, lib_t, bits=11)
+        tuned = [ctx.get_option(k) for k in opts]
+    finally:
+        for k, v in zip(opts, saved):
+            ctx.set_option(k, v)
+    assert np.array_equal(Ft, F), tuned
     maps = ctx.extract_maps(to_device(img), logfx.Params(*lib_t), bits=11)
     torch.cuda.synchronize()
     for k in ("L1", "L2", "Z1", "Z2"):
