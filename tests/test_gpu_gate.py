@@ -355,24 +355,20 @@ def _region_scene(gy, gx, R, seed0):
     return np.ascontiguousarray(np.concatenate(rows, axis=0))
 
 
-@pytest.mark.parametrize("gy,gx,R,median_size", [(2, 4, 256, 5), (4, 2, 128, 3), (1, 1, 384, 5)])
-def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
-    """gate_region: one image, one global deviation per mask, and a gate
-    decision per R x R region.  The features of each region are the oracle's
-    features of that region's part of the whole image's crossing maps (bit
-    for bit); the logits match the oracle network; the output is the
-    oracle's smoothed map F in the smoothed regions and its unsmoothed map E
-    elsewhere (band rule), with the median reading across region borders."""
+def _check_regions(ctx, img, R, bits, median_size, theta_seed, path):
+    """Features, logits, decisions and output of a gate_region call against
+    the oracle chain (features bit for bit, logits within LOGIT_TOL, output F
+    or E per region under the band rule)."""
     import torch
     from parity import compare
-    img = _region_scene(gy, gx, R, 20_000 + 97 * R)
+    gy, gx = img.shape[0] // R, img.shape[1] // R
     orc_t, lib_t = masks()
     o = run_oracle(img, orc_t, smooth=True, median_size=median_size)
     regions = [(y, x) for y in range(gy) for x in range(gx)]
     crop = lambda a, y, x: a[y * R:(y + 1) * R, x * R:(x + 1) * R]
-    feats_ref = np.stack([og.features(crop(img, y, x), crop(o["Z1"], y, x), crop(o["Z2"], y, x), 11)
+    feats_ref = np.stack([og.features(crop(img, y, x), crop(o["Z1"], y, x), crop(o["Z2"], y, x), bits)
                           for y, x in regions])
-    theta = og.init(103)
+    theta = og.init(theta_seed)
     theta[og.NPARAM - 1] = 0.0
     z0, _ = og.forward(theta, feats_ref)
     # the output bias splits the regions between both choices, well away from 0
@@ -383,9 +379,9 @@ def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
     ctx.gate_set_params(theta)
     params = logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, median_size=median_size, gate_region=R)
     dev = to_device(img)
-    feats = ctx.gate_features(dev, params, bits=11)
-    logits, dec = ctx.gate(dev, params, bits=11)
-    out, rep = ctx.extract(dev, params, bits=11, report=True)
+    feats = ctx.gate_features(dev, params, bits=bits)
+    logits, dec = ctx.gate(dev, params, bits=bits)
+    out, rep = ctx.extract(dev, params, bits=bits, report=True)
     torch.cuda.synchronize()
     got = feats.float().cpu().numpy().astype(np.float64)
     assert got.shape == (len(regions), 3, 128, 128)
@@ -397,7 +393,7 @@ def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
     assert np.array_equal(dec[sure], (z_ref[sure] > 0).astype(np.uint8))
     if len(regions) > 1:
         assert 0 < dec.sum() < len(regions)
-    assert rep["gated"] == 1 and rep["gate_fallback"] == 0
+    assert rep["gated"] == 1 and rep["gate_fallback"] == 0 and rep["path"] == path
     assert rep["regions"] == len(regions) and rep["regions_smoothed"] == int(dec.sum())
     assert rep["sigma_g"] == pytest.approx(list(o["stats"][:2]), rel=1e-12)
     ref = o["E"].copy()
@@ -405,6 +401,47 @@ def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
         if dec[q]:
             ref[y * R:(y + 1) * R, x * R:(x + 1) * R] = crop(o["F"], y, x)
     compare(out.cpu().numpy(), {**o, "F": ref}, smooth=True, median_size=median_size)
+
+
+@pytest.mark.parametrize("gy,gx,R,median_size", [(2, 4, 256, 5), (4, 2, 128, 3), (1, 1, 384, 5)])
+def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
+    """gate_region: one image, one global deviation per mask, and a gate
+    decision per R x R region.  The features of each region are the oracle's
+    features of that region's part of the whole image's crossing maps (bit
+    for bit); the logits match the oracle network; the output is the
+    oracle's smoothed map F in the smoothed regions and its unsmoothed map E
+    elsewhere (band rule), with the median reading across region borders."""
+    img = _region_scene(gy, gx, R, 20_000 + 97 * R)
+    _check_regions(ctx, img, R, 11, median_size, 103, logfx.PATH_INT32)
+
+
+def test_gate_regions_fp64_path(ctx):
+    """The same on the FP64 path: 16-bit pixels whose LoG sums leave int32,
+    2 x 4 regions of 128^2 with different noise levels."""
+    rng = np.random.default_rng(404)
+    base = rng.integers(20000, 40000, (256, 512)).astype(np.float64)
+    for y in range(2):
+        for x in range(4):
+            base[y * 128:(y + 1) * 128, x * 128:(x + 1) * 128] += \
+                rng.normal(0, 300.0 * (1 + 3 * ((y * 4 + x) % 3)), (128, 128))
+    img = np.clip(np.rint(base), 0, 65535).astype(np.uint16)
+    _check_regions(ctx, img, 128, 16, 5, 107, logfx.PATH_FP64)
+
+
+def test_gate_regions_without_gate_parameters():
+    """With no gate parameters a gate_region call falls back to always
+    smoothing, as GATE does: the ALWAYS output, gate_fallback set, no
+    regions reported."""
+    import torch
+    _, lib_t = masks()
+    img = to_device(_region_scene(1, 2, 128, 31_000))
+    with logfx.Context(0) as c:
+        out, rep = c.extract(img, logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE, gate_region=128), bits=11,
+                             report=True)
+        ref = c.extract(img, logfx.Params(*lib_t, smooth=True), bits=11)
+        torch.cuda.synchronize()
+    assert rep["gate_fallback"] == 1 and rep["gated"] == 0 and rep["regions"] == 0 and rep["smoothed"] == 1
+    assert torch.equal(out, ref)
 
 
 def test_gate_regions_refused_in_batches(ctx):
