@@ -335,6 +335,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=8192, help="scene side (8192 = the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-transfers", action="store_true",
+                    help="skip the host transfer timing after the timed region")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (strip heights stay at their defaults)")
     ap.add_argument("--store-z", type=int, default=1, choices=[0, 1],
@@ -431,6 +433,36 @@ def main():
     copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del csrc, cdst
     px = H * W
+    # host <-> device transfers (the transfer / kernel split of the paper's
+    # Table 6), after the timed region and not part of `value`: the image in
+    # from pinned host memory and the output map back to pinned host memory
+    transfers = None
+    if not args.no_transfers:
+        h_img = torch.empty(bufs[0].shape, dtype=bufs[0].dtype, pin_memory=True)
+        h_img.copy_(bufs[0].cpu())
+        h_out = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+        d_in = torch.empty_like(bufs[0])
+        d_in.copy_(h_img, non_blocking=True)
+        h_out.copy_(out, non_blocking=True)
+        torch.cuda.synchronize()
+        t0, t1, t2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        reps = 5
+        t0.record(stream)
+        for _ in range(reps):
+            d_in.copy_(h_img, non_blocking=True)
+        t1.record(stream)
+        for _ in range(reps):
+            h_out.copy_(out, non_blocking=True)
+        t2.record(stream)
+        torch.cuda.synchronize()
+        h2d, d2h = t0.elapsed_time(t1) / reps, t1.elapsed_time(t2) / reps
+        nin, nout = h_img.numel() * h_img.element_size(), h_out.numel()
+        transfers = {"h2d_ms": round(h2d, 4), "d2h_ms": round(d2h, 4),
+                     "h2d_GBs": round(nin / (h2d * 1e-3) / 1e9, 1), "d2h_GBs": round(nout / (d2h * 1e-3) / 1e9, 1),
+                     "pcie_inclusive_Mpixel_s": round(px / ((h2d + ms_step + d2h) * 1e-3) / 1e6, 1),
+                     "kernel_share": round(ms_step / (h2d + ms_step + d2h), 4)}
+        del h_img, h_out, d_in
+        log(f"transfers: in {h2d:.3f} ms, out {d2h:.3f} ms")
     value = px / (ms_step * 1e-3) / 1e6
     avg = [k / max(calls, 1) for k in kern_ms]
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step, kernels (ms) p1={avg[0]:.4f} "
@@ -482,6 +514,7 @@ def main():
                        "pass2": round(avg[2], 4)},
         "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
         "roofline": roofline,
+        "transfers": transfers,
     }
     ctx.close()
     if args.copy_mib > 0:
