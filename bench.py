@@ -117,6 +117,11 @@ def cpu_baseline(img, orc_taps, min_seconds: float = 10.0):
     oracle.extract(crop, orc_taps[0], orc_taps[1], nthreads=1)
     res["value_1_thread"] = crop.size / (time.perf_counter() - t0) / 1e6
     res["sample_1_thread"] = f"{crop.shape[0]}x{crop.shape[1]} crop of the scene, 1 run"
+    # and two threads, the thread count of the paper's CPU program (the
+    # oracle splits rows between them, not LoG branches)
+    t0 = time.perf_counter()
+    oracle.extract(crop, orc_taps[0], orc_taps[1], nthreads=2)
+    res["value_2_threads"] = crop.size / (time.perf_counter() - t0) / 1e6
     return res
 
 
