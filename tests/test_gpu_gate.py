@@ -403,7 +403,11 @@ def _check_regions(ctx, img, R, bits, median_size, theta_seed, path):
     compare(out.cpu().numpy(), {**o, "F": ref}, smooth=True, median_size=median_size)
 
 
-@pytest.mark.parametrize("gy,gx,R,median_size", [(2, 4, 256, 5), (4, 2, 128, 3), (1, 1, 384, 5)])
+# 144: region rows start inside a pass-2 column word (bit 16) and region
+# columns inside tiles, so both the per-pixel choice across a word's region
+# boundary and tiles spanning regions are exercised
+@pytest.mark.parametrize("gy,gx,R,median_size", [(2, 4, 256, 5), (4, 2, 128, 3), (1, 1, 384, 5), (2, 4, 144, 5),
+                                                 (4, 2, 144, 3)])
 def test_gate_regions_seamless(ctx, gy, gx, R, median_size):
     """gate_region: one image, one global deviation per mask, and a gate
     decision per R x R region.  The features of each region are the oracle's
