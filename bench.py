@@ -237,6 +237,21 @@ def bench_gated(args):
     res["seamless_gated"] = {"ms_per_step": round(ms, 4), "Mpixel_s": round(px / (ms * 1e-3) / 1e6, 1),
                              "region": T, "smoothed_regions": int(sum(seam_dec))}
     log(f"seamless gated: {ms:.3f} ms/step")
+    # the plain always-smoothed form of the same calls, for the gated vs plain comparison
+    p_always = logfx.Params(*lib_taps, smooth=logfx.SMOOTH_ALWAYS)
+    for _ in range(args.warmup):
+        for bt, bo in zip(bands, bouts):
+            ctx.extract(bt, p_always, bo, bits=11)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        for bt, bo in zip(bands, bouts):
+            ctx.extract(bt, p_always, bo, bits=11)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_a = start.elapsed_time(stop) / args.steps
+    res["seamless_always"] = {"ms_per_step": round(ms_a, 4), "Mpixel_s": round(px / (ms_a * 1e-3) / 1e6, 1)}
+    log(f"seamless always: {ms_a:.3f} ms/step")
     # the per-region decisions, in the tiles' order
     seam = np.concatenate([ctx.gate(bt, params, bits=11)[1].cpu().numpy() for bt in bands]).astype(np.int64)
     ctx.close()
