@@ -1,8 +1,8 @@
 """Test infrastructure: FP64 oracle of the smoothing gate (features, network,
 loss, gradients, AdamW).  Not part of the product; only tests import it.
 
-The paper leaves the choice to smooth or not to the user ("depending on the
-noise content in the extracted image", abstract; Sec. 4).  The gate makes
+The paper leaves the choice to smooth or not to the user, who makes it
+from how noisy the extracted map is (abstract; Sec. 4).  The gate makes
 that choice per tile with a small CNN:
 
   features  3 x 128 x 128 per tile: per cell (an area-downsample of the tile),
@@ -12,7 +12,9 @@ that choice per tile with a small CNN:
             conv (32->32) ReLU  [128 -> 64 -> 32 -> 16], global average
             pool, linear 32 -> 1 logit;
   loss      binary cross-entropy with logits, mean over the batch;
-  optimiser AdamW on FP32 master weights.
+  optimiser AdamW on FP32 master weights;
+  labels    smoothing_label / tile_label below: the rule that writes every
+            stored training and evaluation label.
 
 The GPU keeps the features, the convolution weights and the stored
 activations in bfloat16 and accumulates in FP32.  This oracle evaluates in
@@ -175,3 +177,39 @@ def init(seed):
         else:
             d[name] = np.zeros(shape)
     return flatten(d).astype(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------- labels
+def smoothing_label(E_noisy, F_noisy, E_clean):
+    """The smoothing label of one tile (the reading of the labelling rule:
+    the abstract and Sec. 4 let the noise in the extracted map decide the
+    hybrid median of Sec. 3.4, and give no rule).
+
+    E_noisy, F_noisy: the unsmoothed and smoothed maps of the noisy tile;
+    E_clean: the unsmoothed map of its noise-free twin.  With N pixels,
+    n_raw = #(E_noisy != E_clean) and n_med = #(F_noisy != E_clean), so
+    D_raw = n_raw / N and D_med = n_med / N.  The median is worth applying
+    when it lowers the disagreement by more than 1 % of itself: label 1 iff
+    n_raw > 0 and D_med < 0.99 D_raw, decided exactly on the integers as
+    100 n_med < 99 n_raw (a tile with D_raw = 0 gets 0).  The best-choice
+    output of the tile is F_noisy for label 1, else E_noisy.
+
+    Returns (d_raw, d_med, label, diff), diff = #(E_noisy != F_noisy): the
+    pixels a wrong choice costs against the best-choice output."""
+    E_noisy, F_noisy, E_clean = (np.asarray(a) for a in (E_noisy, F_noisy, E_clean))
+    N = E_clean.size
+    n_raw = int(np.count_nonzero(E_noisy != E_clean))
+    n_med = int(np.count_nonzero(F_noisy != E_clean))
+    label = int(n_raw > 0 and 100 * n_med < 99 * n_raw)
+    return n_raw / N, n_med / N, label, int(np.count_nonzero(E_noisy != F_noisy))
+
+
+def tile_label(noisy, clean, taps, **kw):
+    """smoothing_label of a tile from its pixels and its noise-free twin's:
+    the oracle pipeline (oracle.extract, with the masks taps and the
+    parameters kw) on both, the noisy tile unsmoothed and smoothed, the
+    twin unsmoothed."""
+    import oracle
+    o = oracle.extract(noisy, taps[0], taps[1], smooth=True, want_intermediates=True, **kw)
+    c = oracle.extract(clean, taps[0], taps[1], smooth=False, **kw)
+    return smoothing_label(o["E"], o["F"], c["F"])

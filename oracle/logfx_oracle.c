@@ -163,8 +163,9 @@ void orc_log_response(const void *img, int dtype, long H, long W, long pitch,
  *    the crossing (each opposite-sign pair marks exactly one pixel);
  *  - p with L(p) == 0 is a crossing if its left/right or its up/down
  *    neighbours have opposite signs;
- *  - strength c(p) = max - min of L over p and its four neighbours (the
- *    difference between the positive maximum and the negative minimum);
+ *  - strength c(p) = max - min of L over p and its four neighbours (at a
+ *    crossing the largest value is positive and the smallest negative, so
+ *    this is the span across zero that Sec. 3.2 thresholds);
  *  - Z(p) = c(p) if p is a crossing and c(p) > zc_thresh, else 0.
  * ---------------------------------------------------------------------- */
 static int opposite(double a, double b) { return (a < 0 && b > 0) || (a > 0 && b < 0); }

@@ -1,6 +1,7 @@
 """Writes tests/golden/config5_labels.npz: the oracle's best-choice labels of
 the four-band 16384^2 workload cut into 2048^2 tiles (scenes.config5_*).
-Calls only oracle/ and scenes.
+Calls only oracle/ and scenes; the labelling rule is
+oracle.gate.smoothing_label (via oracle.gate.tile_label).
 
 Per tile: E_noisy and F_noisy are the oracle's unsmoothed and hybrid-median
 maps of the noisy tile, E_clean the unsmoothed map of the noise-free tile;
@@ -22,6 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
+from oracle import gate  # noqa: E402
 from paper_1304_3992_amd import scenes  # noqa: E402
 
 
@@ -36,12 +38,8 @@ def main():
     index = scenes.config5_index(size, tile)
     for k, (b, ty, tx) in enumerate(index):
         noisy, clean, sigma, density = scenes.config5_tile(base, b, ty, tx, tile)
-        o = oracle.extract(noisy, taps[0], taps[1], smooth=True, want_intermediates=True)
-        c = oracle.extract(clean, taps[0], taps[1], smooth=False)
-        d_raw = float((o["E"] != c["F"]).mean())
-        d_med = float((o["F"] != c["F"]).mean())
-        rows.append((d_raw, d_med, int(d_raw > 0 and d_med < 0.99 * d_raw), int((o["E"] != o["F"]).sum()),
-                     sigma, density))
+        d_raw, d_med, label, diff = gate.tile_label(noisy, clean, taps)
+        rows.append((d_raw, d_med, label, diff, sigma, density))
         shas.append(scenes.sha256(noisy))
         if (k + 1) % 16 == 0:
             print(f"{k + 1}/{len(index)} tiles, {time.time() - t0:.0f} s", flush=True)

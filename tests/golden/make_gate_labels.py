@@ -1,5 +1,6 @@
 """Writes tests/golden/gate_labels.npz: the oracle's smoothing labels of the
-gate's training tiles (scenes.gate_tile).  Calls only oracle/ and scenes.
+gate's training tiles (scenes.gate_tile).  Calls only oracle/ and scenes; the labelling rule is
+oracle.gate.smoothing_label (via oracle.gate.tile_label).
 
 Per tile (the reading of the benchmark's labelling rule): E_noisy and
 F_noisy are the oracle's unsmoothed and hybrid-median maps of the noisy tile,
@@ -23,16 +24,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
+from oracle import gate  # noqa: E402
 from paper_1304_3992_amd import scenes  # noqa: E402
 
 
 def label_tile(i, size, taps, base_seed, band):
     noisy, clean, sigma, density = scenes.gate_tile(i, size, base_seed, band=band)
-    o = oracle.extract(noisy, taps[0], taps[1], smooth=True, want_intermediates=True)
-    c = oracle.extract(clean, taps[0], taps[1], smooth=False)
-    d_raw = float((o["E"] != c["F"]).mean())
-    d_med = float((o["F"] != c["F"]).mean())
-    return d_raw, d_med, int(d_raw > 0 and d_med < 0.99 * d_raw), sigma, density
+    d_raw, d_med, label, _ = gate.tile_label(noisy, clean, taps)
+    return d_raw, d_med, label, sigma, density
 
 
 def main():

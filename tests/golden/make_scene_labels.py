@@ -2,7 +2,8 @@
 four-band scenes built like the 16384^2 benchmark workload (scenes.config5_*)
 but smaller and from other seeds, cut into tiles -- training data of the
 smoothing gate whose test is the benchmark scene itself (seed 5).
-Calls only oracle/ and scenes.
+Calls only oracle/ and scenes; the labelling rule is
+oracle.gate.smoothing_label (via oracle.gate.tile_label).
 
 Per tile, as in make_gate_labels.py: D_raw = mean(E_noisy != E_clean),
 D_med = mean(F_noisy != E_clean), label = [D_raw > 0 and D_med < 0.99 D_raw];
@@ -22,6 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
+from oracle import gate  # noqa: E402
 from paper_1304_3992_amd import scenes  # noqa: E402
 
 
@@ -37,12 +39,8 @@ def main():
         base = scenes.config5_base(size, seed)
         for b, ty, tx in scenes.config5_index(size, tile):
             noisy, clean, sigma, density = scenes.config5_tile(base, b, ty, tx, tile, seed)
-            o = oracle.extract(noisy, taps[0], taps[1], smooth=True, want_intermediates=True)
-            c = oracle.extract(clean, taps[0], taps[1], smooth=False)
-            d_raw = float((o["E"] != c["F"]).mean())
-            d_med = float((o["F"] != c["F"]).mean())
-            rows.append((seed, b, ty, tx, d_raw, d_med, int(d_raw > 0 and d_med < 0.99 * d_raw),
-                         int((o["E"] != o["F"]).sum()), sigma, density))
+            d_raw, d_med, label, diff = gate.tile_label(noisy, clean, taps)
+            rows.append((seed, b, ty, tx, d_raw, d_med, label, diff, sigma, density))
         print(f"scene {seed}: {len(rows)} tiles, {time.time() - t0:.0f} s", flush=True)
     a = np.array(rows, dtype=np.float64)
     np.savez_compressed(os.path.join(HERE, "gate_labels_scenes.npz"), scene_seed=a[:, 0].astype(np.int32),

@@ -1,6 +1,7 @@
 """Pins of the gate oracle (no GPU): rounding, convolution, gradients and the
 optimiser step against library routines and finite differences; features
-against a per-cell brute force; labels against their definition."""
+against a per-cell brute force.  The labelling rule has its own pins in
+test_gate_labels.py."""
 import numpy as np
 import pytest
 import torch
