@@ -105,7 +105,6 @@ int main() {
     // NULL contexts are refused before any device call
     uint8_t *out = reinterpret_cast<uint8_t *>(0x2000);
     EXPECT(logfx_extract(nullptr, &img, &p, out, nullptr, nullptr) == LOGFX_EINVAL);
-    EXPECT(logfx_extract_noalloc(nullptr, &img, &p, out, nullptr, nullptr) == LOGFX_EINVAL);
     EXPECT(logfx_extract_batch(nullptr, 1, &img, &p, &out, nullptr, nullptr) == LOGFX_EINVAL);
     EXPECT(logfx_gate(nullptr, 1, &img, &p, nullptr, nullptr, nullptr) == LOGFX_EINVAL);
     EXPECT(logfx_set_option(nullptr, LOGFX_OPT_ROWS1, 64) == LOGFX_EINVAL);
