@@ -2,15 +2,19 @@
 """Benchmark of the LoG feature-extraction pipeline (liblogfx) on one MI355X.
 
 One step = one full pass of the pipeline over one image already resident in
-HBM: pass 1 (both LoG responses, zero crossings, per-tile sums), the
-finalize kernel (global deviation, thresholds) and pass 2 (LoG and zero
-crossings again, 3x3 deviation test, OR, 5x5 hybrid median, output map).
+HBM: pass 1 (both LoG responses, zero crossings, per-tile sums, the
+crossing-strength pair of every pixel stored), the finalize kernel (global
+deviation, thresholds) and pass 2 (3x3 deviation test on the stored
+strengths, OR, 5x5 hybrid median, output map).
 
 Workload (default): the 8192 x 8192 11-bit scene -- 20000 rectangles, 500
 polylines of width 1-3, Gaussian noise sigma 12, 5 % salt-and-pepper --
 with masks 5x5 sigma 0.8 and 9x9 sigma 1.4, threshold 2.0 x the global
 deviation and the 5x5 hybrid median.  Three copies of the input are rotated
 so the 256 MB last-level cache cannot serve a step from the previous one.
+The timed region holds the K steps only; per-kernel times, the spread of
+single steps, the FP64 path, the 512^2 latency and the host transfers are
+measured after it.
 
 Prints one JSON line (see the keys below).  Progress goes to stderr.
 
@@ -37,8 +41,9 @@ METRIC = "Mpixel/s full pipeline, % HBM roofline; gated vs plain at >=99.9% agre
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic ALU operations per output pixel of pass 2, the dominant kernel,
-# counted for the exact orbit-form evaluation the library uses (no halo
+# Algorithmic ALU operations per output pixel of the recomputing pass 2
+# (LOGFX_OPT_STORE_Z = 0: LoG and crossings again, then the deviation), counted
+# for the exact orbit-form evaluation the library uses (no halo
 # recomputation, no address or loop bookkeeping).  For masks of radius 2 and
 # 4 (15 orbits, 6 of them shared by the 5x5 mask):
 PASS2_OPS = {
@@ -88,11 +93,44 @@ def log(msg):
 
 
 def host_cores() -> int:
+    """Threads the CPU work may use: the cores this process may run on,
+    limited to the job's CPU share when the environment states one
+    (OMP_NUM_THREADS; a GPU job of this machine pool gets 16 host threads
+    per GPU, whatever the host's core count)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(16, n))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        n = min(n, int(share))
+    return max(1, n)
+
+
+def cpu_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity,
+            "job_share": os.environ.get("OMP_NUM_THREADS")}
+
+
+# The paper's headline speed-up (Table 7, Sec. 7): its pixel-wise CUDA
+# program on a Tesla C2075 against its two-thread pthreads program on an
+# 8-core Xeon E5620 (2.4 GHz), AWiFS 2000 x 2000 image: 24500 ms / 1182 ms.
+PAPER_SPEEDUP = {"x": round(24500.0 / 1182.0, 1), "gpu": "NVIDIA Tesla C2075",
+                 "cpu": "Intel Xeon E5620 (8 cores, 2.4 GHz), 2-thread pthreads program",
+                 "image": "AWiFS 2000 x 2000", "source": "Table 7, Sec. 7"}
 
 
 def cpu_baseline(img, orc_taps, min_seconds: float = 10.0):
@@ -109,7 +147,8 @@ def cpu_baseline(img, orc_taps, min_seconds: float = 10.0):
         if dt >= min_seconds:
             break
     res = {"value": runs * img.size / dt / 1e6, "unit": "Mpixel/s", "cores": n, "kind": "oracle",
-           "sample": f"whole {img.shape[0]}x{img.shape[1]} scene, {runs} runs, {dt:.1f} s"}
+           "sample": f"whole {img.shape[0]}x{img.shape[1]} scene, {runs} runs, {dt:.1f} s",
+           "cpu": cpu_info()}
     # context: one thread on a 2048^2 crop (the paper's CPU program ran one
     # thread per LoG branch, Sec. 6.1)
     crop = np.ascontiguousarray(img[:2048, :2048])
@@ -129,7 +168,8 @@ def _c5_tile(args):
     import numpy as np
     from paper_1304_3992_amd import scenes
     b, ty, tx = args
-    return scenes.config5_tile(_C5_BASE, b, ty, tx)[0]
+    t = scenes.config5_tile(_C5_BASE, b, ty, tx)[0]
+    return t, scenes.sha256(t)
 
 
 _C5_BASE = None
@@ -144,12 +184,16 @@ def bench_gated(args):
     root = os.path.dirname(os.path.abspath(__file__))
     t0 = time.time()
     _C5_BASE = scenes.config5_base()
+    base_sha = scenes.sha256(_C5_BASE)
     index = scenes.config5_index()
     log(f"base scene {time.time() - t0:.0f} s; generating {len(index)} tiles ...")
     # worker processes are forked before anything touches the GPU
     with mp.get_context("fork").Pool(host_cores()) as pool:
-        tiles = pool.map(_c5_tile, index, chunksize=4)
+        made = pool.map(_c5_tile, index, chunksize=4)
     _C5_BASE = None
+    tiles = [t for t, _ in made]
+    tile_shas = [h for _, h in made]
+    del made
     log(f"tiles ready ({time.time() - t0:.0f} s)")
     import torch
     from paper_1304_3992_amd import logfx
@@ -260,7 +304,12 @@ def bench_gated(args):
     if os.path.exists(lab_path):
         d = np.load(lab_path)
         lab, diff = d["label"].astype(np.int64), d["diff"].astype(np.float64)
-        if len(lab) == len(decisions):
+        # the stored labels hold only for the tiles they were computed on
+        same_tiles = (str(d["base_sha"]) == base_sha and len(d["sha"]) == len(tile_shas)
+                      and all(str(a) == b for a, b in zip(d["sha"], tile_shas)))
+        if not same_tiles:
+            log("the generated tiles differ from those of the stored labels: no agreement figure")
+        if same_tiles and len(lab) == len(decisions):
             def agree(dec):
                 return float(1.0 - diff[dec != lab].sum() / px)
             agreement = {"gated": agree(decisions), "always": agree(np.ones_like(lab)),
@@ -355,6 +404,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=8192, help="scene side (8192 = the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64-path run of the scene after the timed region")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the 512^2 single-call latency after the timed region")
     ap.add_argument("--no-transfers", action="store_true",
                     help="skip the host transfer timing after the timed region")
     ap.add_argument("--no-tune", action="store_true",
@@ -417,7 +470,7 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
 
-    ctx.timing_enable(True)
+    # the timed region: K steps and nothing else
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
@@ -426,10 +479,15 @@ def main():
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
+    ms_step = total_ms / args.steps
+    # after it: per-kernel HIP-event times over the same number of steps, on
+    # the stream the kernels run on
+    ctx.timing_enable(True)
+    for i in range(args.steps):
+        ctx.extract(bufs[i % 3], params, out, bits=11)
     kern_ms, calls = ctx.timing_read()
     ctx.timing_enable(False)
-    ms_step = total_ms / args.steps
-    # spread of single steps (after the timed region, not part of `value`)
+    # spread of single steps
     singles = []
     for i in range(min(args.steps, 30)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -439,6 +497,56 @@ def main():
         singles.append((e0, e1))
     torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in singles])
+    # the FP64 path on the same scene: masks on a 23-bit grid (the finest
+    # grid an FP32 tap holds), whose sums exceed the int32 bound
+    fp64 = None
+    if not args.no_fp64:
+        p64 = logfx.Params(logfx.make_log_mask(5, 0.8, 23)[0], logfx.make_log_mask(9, 1.4, 23)[0],
+                           std_k=2.0, smooth=True, median_size=5, median_cascade=cascade)
+        _, rep64 = ctx.extract(bufs[0], p64, out, bits=11, report=True)
+        for i in range(args.warmup):
+            ctx.extract(bufs[i % 3], p64, out, bits=11)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for i in range(args.steps):
+            ctx.extract(bufs[i % 3], p64, out, bits=11)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms64 = start.elapsed_time(stop) / args.steps
+        fp64 = {"ms_per_step": round(ms64, 4), "Mpixel_s": round(H * W / (ms64 * 1e-3) / 1e6, 1),
+                "path": "fp64" if rep64["path"] == logfx.PATH_FP64 else "int32", "mask_grid_bits": 23,
+                "rows_per_strip": [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]}
+        log(f"fp64 path: {ms64:.3f} ms/step")
+    # latency of one call on the 512^2 uint8 image (40 rectangles, noise
+    # sigma 4): it fits in the caches, so launches dominate
+    lat = None
+    if not args.no_latency:
+        small = torch.from_numpy(scenes.config1()).to(dev)
+        sout = torch.empty(small.shape, dtype=torch.uint8, device=dev)
+        for _ in range(max(args.warmup, 3)):
+            ctx.extract(small, params, sout, bits=8)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(50):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.extract(small, params, sout, bits=8)
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        lms = np.array([a.elapsed_time(b) for a, b in evs])
+        wall = []
+        for _ in range(50):
+            t0 = time.perf_counter()
+            ctx.extract(small, params, sout, bits=8)
+            torch.cuda.synchronize()
+            wall.append(time.perf_counter() - t0)
+        lat = {"workload": "512x512 uint8 image, 40 rectangles, noise sigma 4; same masks, threshold and median",
+               "device_ms_p10_p50_p90": [round(float(np.percentile(lms, q)), 4) for q in (10, 50, 90)],
+               "host_wall_ms_p50": round(float(np.median(wall)) * 1e3, 4),
+               "Mpixel_s_p50": round(small.numel() / (float(np.median(lms)) * 1e-3) / 1e6, 1)}
+        del small, sout
+        log(f"512^2 latency: {lat['device_ms_p10_p50_p90'][1]:.4f} ms")
     # a plain device copy of 1 GiB: the HBM bandwidth this machine reaches
     csrc = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     cdst = torch.empty_like(csrc)
@@ -519,6 +627,18 @@ def main():
                      "peak_GBs": HBM_PEAK_GBS,
                      "frac": round(3 * px / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    if dom_name == "pass1_kernel":
+        # frac above counts the operations of the orbit-sum form the kernel
+        # runs; the same time against the 106 multiply-adds of the two
+        # direct-form masks (25 + 81), the work as eq. (1) states it
+        roofline["frac_direct_form_log_fma"] = round(106 * px / (avg[0] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)
+    # why the pipeline cannot sit at 70 % of HBM peak: its arithmetic floor
+    # (pass 1's operations at the VALU peak) against the time its 3 bytes
+    # per pixel take at that fraction of the 8 TB/s
+    roofline["hbm_bar"] = {"target_frac": 0.70,
+                           "pipeline_frac": roofline["hbm_view"]["frac"],
+                           "alu_floor_ms": round(PASS1_OPS_PER_PX * px / (VALU_PEAK_TOPS * 1e12) * 1e3, 4),
+                           "hbm_time_at_target_ms": round(3 * px / (0.70 * HBM_PEAK_GBS * 1e9) * 1e3, 4)}
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -535,6 +655,9 @@ def main():
         "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
         "roofline": roofline,
         "transfers": transfers,
+        "fp64_path": fp64,
+        "latency_512x512_u8": lat,
+        "paper_speedup": PAPER_SPEEDUP,
     }
     ctx.close()
     if args.copy_mib > 0:
@@ -550,6 +673,7 @@ def main():
         log(f"oracle on {host_cores()} host threads ...")
         orc_taps = (oracle.log_mask(5, 0.8, 16)[0], oracle.log_mask(9, 1.4, 16)[0])
         result["cpu_baseline"] = cpu_baseline(img, orc_taps)
+        result["speedup_vs_oracle"] = round(result["value"] / result["cpu_baseline"]["value"], 1)
         log(f"oracle {result['cpu_baseline']['value']:.2f} Mpixel/s")
     print(json.dumps(result), flush=True)
 

@@ -5,18 +5,22 @@
 //   (Sec. 3.2), E_j = [3x3 deviation of Z_j > T_j] (eq. (2)), E = E_1 | E_2,
 //   F = hybrid_median(E) (Sec. 3.4).
 // T_j depends on the global deviation of Z_j, a grid-wide quantity, so the
-// work runs as   pass 1 (LoG, Z, per-tile sums) -> finalize (T_j) ->
-// pass 2 (LoG and Z again with a wider halo, local deviation, OR, median).
+// work runs as   pass 1 (LoG, Z, per-tile sums; by default the pair
+// (Z_1, Z_2) of every pixel stored to HBM) -> finalize (T_j) -> pass 2.
+// Pass 2 normally reads the stored pairs (pass2z_kernel, in
+// logfx_pass2z.hip: deviation, OR and the median on per-lane column words);
+// the recompute form below (pass2_kernel) is the fallback when the pair
+// memory cannot be had: it evaluates the LoG and Z again with a wider halo
+// and takes the median on 64-bit wave-row ballots.
 //
-// Work decomposition.  A workgroup owns an output tile of kTileWaves wave-wide
-// column strips side by side, `rows` rows tall; the input tile plus halo is
-// staged once in LDS as u16 with clamp-to-edge coordinates.  Each lane owns
-// one column and walks down the rows, keeping a ring of 2R+1 rows of
-// horizontal pair sums in registers.  Horizontal neighbours of later
-// stages come from the adjacent lanes (DPP wave shifts on the vector ALU;
-// lanes at the image border take their own value).  The extracted
-// bits of a row are a 64-bit wave ballot; the hybrid median of those bits is
-// computed bit-sliced on the scalar unit, 64 pixels per instruction.
+// Work decomposition of the image-reading passes.  A workgroup owns an
+// output tile of kTileWaves wave-wide column strips side by side, `rows`
+// rows tall; the input tile plus halo is staged once in LDS as u16 with
+// clamp-to-edge coordinates.  Each lane owns one column and walks down the
+// rows, keeping a ring of 2R+1 rows of horizontal pair sums in registers.
+// Horizontal neighbours of later stages come from the adjacent lanes (DPP
+// wave shifts on the vector ALU; lanes at the image border take their own
+// value).
 //
 // Exactness.  Mask taps are integers k on a power-of-two grid, and the LoG
 // is evaluated on D4 orbit sums of pixels: L = sum_o k_o * O_o.  Every sum is
