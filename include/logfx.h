@@ -332,9 +332,26 @@ int logfx_gate_set_params(logfx_ctx *ctx, const float *theta, int64_t n);
 /* Copy the parameters to HOST memory (waits for the device). */
 int logfx_gate_get_params(logfx_ctx *ctx, float *theta, int64_t n);
 /* Parameters from / to a file: the 8 bytes "LOGFXGT1", int32 parameter
- * count, int32 0, then the FP32 values, all little-endian. */
+ * count, int32 0, then the FP32 values, all little-endian.  logfx_gate_load
+ * also takes a training-state file (below) and uses its parameters; like
+ * logfx_gate_set_params it resets the optimiser state.  A missing, short or
+ * corrupt file gives LOGFX_EINVAL and leaves the context's gate as it was
+ * (a context without parameters then runs LOGFX_SMOOTH_GATE as ALWAYS and
+ * reports gate_fallback). */
 int logfx_gate_load(logfx_ctx *ctx, const char *path);
 int logfx_gate_save(logfx_ctx *ctx, const char *path);
+
+/* Training state to / from a file, so that training can stop and resume
+ * with the same result as an uninterrupted run: the 8 bytes "LOGFXGS1",
+ * int32 parameter count, int32 version 1, int64 AdamW step count, then
+ * LOGFX_GATE_NPARAM FP32 parameters, first moments and second moments,
+ * then a uint64 FNV-1a (64-bit) checksum of every byte before it; all
+ * little-endian.  Saving waits for the device and needs parameters in the
+ * context.  Loading checks the size, header, checksum and values (finite,
+ * second moments >= 0) before it changes anything: LOGFX_EINVAL on any
+ * failure, with the context's gate left as it was. */
+int logfx_gate_save_state(logfx_ctx *ctx, const char *path);
+int logfx_gate_load_state(logfx_ctx *ctx, const char *path);
 
 /* Logits of B samples (1 <= B <= LOGFX_GATE_MAX_BATCH).  logits: DEVICE
  * float[B]. */

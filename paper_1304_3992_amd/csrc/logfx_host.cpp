@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1089,6 +1090,56 @@ void cache_store(const char *path, const std::string &key, const logfx_tune_resu
     f << buf;
 }
 
+
+// FNV-1a, 64-bit: the checksum of a training-state file.
+uint64_t fnv1a64(const void *data, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Training state read from a LOGFXGS1 file: parameters, AdamW moments, step.
+struct GateState {
+    std::vector<float> theta, m, v;
+    int64_t step = 0;
+};
+
+// Reads a file written by logfx_gate_save_state; checks the header, the
+// sizes and the checksum before anything reaches the context.
+int read_gate_state(logfx_ctx *ctx, const char *path, GateState &st) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return set_err(ctx, LOGFX_EINVAL, "cannot open %s", path);
+    std::vector<char> bytes((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    const size_t n = gate::kNParam, body = 8 + 8 + 8 + 3 * n * sizeof(float);
+    if (bytes.size() != body + 8 || std::memcmp(bytes.data(), "LOGFXGS1", 8) != 0)
+        return set_err(ctx, LOGFX_EINVAL, "%s is not a gate training-state file of %d parameters", path,
+                       gate::kNParam);
+    int32_t hdr[2];
+    std::memcpy(hdr, bytes.data() + 8, sizeof hdr);
+    uint64_t sum;
+    std::memcpy(&sum, bytes.data() + body, sizeof sum);
+    if (hdr[0] != gate::kNParam || hdr[1] != 1)
+        return set_err(ctx, LOGFX_EINVAL, "%s: %d parameters, version %d (expected %d, 1)", path, hdr[0], hdr[1],
+                       gate::kNParam);
+    if (fnv1a64(bytes.data(), body) != sum) return set_err(ctx, LOGFX_EINVAL, "%s: checksum mismatch", path);
+    std::memcpy(&st.step, bytes.data() + 16, sizeof st.step);
+    if (st.step < 0) return set_err(ctx, LOGFX_EINVAL, "%s: negative step count", path);
+    st.theta.resize(n);
+    st.m.resize(n);
+    st.v.resize(n);
+    const char *q = bytes.data() + 24;
+    std::memcpy(st.theta.data(), q, n * sizeof(float));
+    std::memcpy(st.m.data(), q + n * sizeof(float), n * sizeof(float));
+    std::memcpy(st.v.data(), q + 2 * n * sizeof(float), n * sizeof(float));
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(st.theta[i]) || !std::isfinite(st.m[i]) || !std::isfinite(st.v[i]) || st.v[i] < 0.0f)
+            return set_err(ctx, LOGFX_EINVAL, "%s: value %zu is not a valid parameter or moment", path, i);
+    return LOGFX_OK;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -1333,13 +1384,21 @@ int logfx_gate_get_params(logfx_ctx *ctx, float *theta, int64_t n) {
 
 int logfx_gate_load(logfx_ctx *ctx, const char *path) {
     if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
     if (!path) return set_err(ctx, LOGFX_EINVAL, "path is NULL");
     std::ifstream f(path, std::ios::binary);
     if (!f) return set_err(ctx, LOGFX_EINVAL, "cannot open %s", path);
     char magic[8];
+    f.read(magic, 8);
+    if (f && std::memcmp(magic, "LOGFXGS1", 8) == 0) {   // a training-state file: its parameters
+        f.close();
+        GateState st;
+        const int rc = read_gate_state(ctx, path, st);
+        if (rc != LOGFX_OK) return rc;
+        return logfx_gate_set_params(ctx, st.theta.data(), gate::kNParam);
+    }
     int32_t hdr[2];
     std::vector<float> theta(gate::kNParam);
-    f.read(magic, 8);
     f.read(reinterpret_cast<char *>(hdr), sizeof hdr);
     if (!f || std::memcmp(magic, "LOGFXGT1", 8) != 0 || hdr[0] != gate::kNParam || hdr[1] != 0)
         return set_err(ctx, LOGFX_EINVAL, "%s is not a gate parameter file of %d values", path, gate::kNParam);
@@ -1360,6 +1419,56 @@ int logfx_gate_save(logfx_ctx *ctx, const char *path) {
     f.write(reinterpret_cast<const char *>(hdr), sizeof hdr);
     f.write(reinterpret_cast<const char *>(theta.data()), sizeof(float) * gate::kNParam);
     if (!f) return set_err(ctx, LOGFX_EINVAL, "cannot write %s", path);
+    return LOGFX_OK;
+}
+
+int logfx_gate_save_state(logfx_ctx *ctx, const char *path) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!path) return set_err(ctx, LOGFX_EINVAL, "path is NULL");
+    auto &G = ctx->gate;
+    if (!G.loaded) return set_err(ctx, LOGFX_EINVAL, "the gate has no parameters");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
+    const size_t n = gate::kNParam, vb = n * sizeof(float), body = 24 + 3 * vb;
+    std::vector<char> bytes(body + 8);
+    std::memcpy(bytes.data(), "LOGFXGS1", 8);
+    const int32_t hdr[2] = {gate::kNParam, 1};
+    std::memcpy(bytes.data() + 8, hdr, sizeof hdr);
+    const int64_t step = G.step;
+    std::memcpy(bytes.data() + 16, &step, sizeof step);
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(bytes.data() + 24, G.theta, vb, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(bytes.data() + 24 + vb, G.m, vb, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(bytes.data() + 24 + 2 * vb, G.v, vb, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_err(ctx, e, "gate state");
+    const uint64_t sum = fnv1a64(bytes.data(), body);
+    std::memcpy(bytes.data() + body, &sum, sizeof sum);
+    std::ofstream f(path, std::ios::binary | std::ios::trunc);
+    f.write(bytes.data(), (std::streamsize)bytes.size());
+    if (!f) return set_err(ctx, LOGFX_EINVAL, "cannot write %s", path);
+    return LOGFX_OK;
+}
+
+int logfx_gate_load_state(logfx_ctx *ctx, const char *path) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!path) return set_err(ctx, LOGFX_EINVAL, "path is NULL");
+    GateState st;
+    int rc = read_gate_state(ctx, path, st);
+    if (rc != LOGFX_OK) return rc;
+    if ((rc = logfx_gate_set_params(ctx, st.theta.data(), gate::kNParam)) != LOGFX_OK) return rc;
+    auto &G = ctx->gate;
+    DeviceGuard dg(ctx->device);
+    const size_t vb = gate::kNParam * sizeof(float);
+    hipError_t e;
+    if ((e = hipMemcpy(G.m, st.m.data(), vb, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(G.v, st.v.data(), vb, hipMemcpyHostToDevice)) != hipSuccess) {
+        G.loaded = false;
+        return hip_err(ctx, e, "gate state");
+    }
+    G.step = st.step;
     return LOGFX_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_set_option", "logfx_get_option", "logfx_tune",
            "logfx_gate_features", "logfx_gate_set_params", "logfx_gate_get_params",
            "logfx_gate_load", "logfx_gate_save", "logfx_gate_forward", "logfx_gate_backward",
-           "logfx_gate_step", "logfx_gate"]
+           "logfx_gate_step", "logfx_gate", "logfx_gate_save_state", "logfx_gate_load_state"]
 GATE_NPARAM, GATE_CELLS, GATE_MAX_BATCH = 14369, 128, 4096
 OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH, OPT_STORE_Z = 1, 2, 3, 4, 5
 ALLOW_INEXACT = 1
@@ -144,6 +144,8 @@ def load(path: str | None = None):
             ("logfx_gate_get_params", [P, FP, ctypes.c_int64]),
             ("logfx_gate_load", [P, ctypes.c_char_p]),
             ("logfx_gate_save", [P, ctypes.c_char_p]),
+            ("logfx_gate_save_state", [P, ctypes.c_char_p]),
+            ("logfx_gate_load_state", [P, ctypes.c_char_p]),
             ("logfx_gate_forward", [P, ctypes.c_int32, P, P, P, P]),
             ("logfx_gate_backward", [P, ctypes.c_int32, P, P, P, P, P, P]),
             ("logfx_gate_step", [P, P, ctypes.c_double, P]),
@@ -393,6 +395,12 @@ class Context:
 
     def gate_save(self, path: str):
         _check(self.lib.logfx_gate_save(self.ptr, os.fsencode(path)), self.ptr)
+
+    def gate_save_state(self, path: str):
+        _check(self.lib.logfx_gate_save_state(self.ptr, os.fsencode(path)), self.ptr)
+
+    def gate_load_state(self, path: str):
+        _check(self.lib.logfx_gate_load_state(self.ptr, os.fsencode(path)), self.ptr)
 
     @staticmethod
     def _batch(feats, idx, B):

@@ -187,6 +187,8 @@ def test_gate_entry_points_reject_null_context(lib):
     assert lib.logfx_gate_get_params(None, tp, logfx.GATE_NPARAM) == E
     assert lib.logfx_gate_load(None, b"/nonexistent") == E
     assert lib.logfx_gate_save(None, b"/nonexistent") == E
+    assert lib.logfx_gate_save_state(None, b"/nonexistent") == E
+    assert lib.logfx_gate_load_state(None, b"/nonexistent") == E
     assert lib.logfx_gate_forward(None, 1, None, None, None, None) == E
     assert lib.logfx_gate_backward(None, 1, None, None, None, None, None, None) == E
     assert lib.logfx_gate_step(None, None, 1e-3, None) == E

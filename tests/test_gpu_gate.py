@@ -174,6 +174,78 @@ def test_parameters_round_trip_file(ctx, tmp_path):
         assert e.value.code == logfx.EINVAL
 
 
+def test_training_state_resumes_exactly(ctx, tmp_path):
+    """Training stopped after some steps, saved with its AdamW moments and
+    step count, and resumed in a fresh context ends with the same
+    parameters, bit for bit, as the uninterrupted run; a corrupted or
+    truncated state file is refused with the context left as it was."""
+    import torch
+    rng = np.random.default_rng(191)
+    N = 96
+    feats = rng.random((N, 3, 128, 128)) * 0.3
+    y = rng.random(N) < 0.5
+    feats[y, 2] += 0.4
+    fd = _bf16_dev(feats)
+    lab = torch.tensor(y.astype(np.float32), device="cuda")
+    theta0 = og.init(192)
+
+    def steps(c, it0, it1):
+        g = torch.empty(og.NPARAM, dtype=torch.float32, device="cuda")
+        for it in range(it0, it1):
+            idx = torch.from_numpy(np.random.default_rng(500 + it).choice(N, 32, replace=False)
+                                   .astype(np.int32)).cuda()
+            c.gate_backward(fd, lab, idx, grad=g)
+            c.gate_step(2e-3, g)
+
+    ctx.gate_set_params(theta0)
+    steps(ctx, 0, 12)
+    whole = ctx.gate_get_params()
+    ctx.gate_set_params(theta0)
+    steps(ctx, 0, 7)
+    path = str(tmp_path / "state.bin")
+    ctx.gate_save_state(path)
+    with logfx.Context(0) as c2:
+        c2.gate_load_state(path)
+        steps(c2, 7, 12)
+        resumed = c2.gate_get_params()
+    assert np.array_equal(resumed, whole)
+    # the parameters alone (gate_load of the state file) restart the moments
+    with logfx.Context(0) as c3:
+        c3.gate_load(path)
+        steps(c3, 7, 12)
+        assert not np.array_equal(c3.gate_get_params(), whole)
+    raw = open(path, "rb").read()
+    before = ctx.gate_get_params()
+    for bad in (raw[:-1], raw[:100] + bytes([raw[100] ^ 1]) + raw[101:], b"LOGFXGT1" + raw[8:]):
+        with open(path, "wb") as f:
+            f.write(bad)
+        with pytest.raises(logfx.LogfxError) as e:
+            ctx.gate_load_state(path)
+        assert e.value.code == logfx.EINVAL
+        assert np.array_equal(ctx.gate_get_params(), before)
+
+
+def test_missing_gate_file_falls_back_to_always(ctx, tmp_path):
+    """A missing or corrupt gate file leaves a fresh context without
+    parameters: SMOOTH_GATE then runs as ALWAYS and the report says so."""
+    import torch
+    img = scenes.gate_tile(11)[0]
+    _, lib_t = masks()
+    with logfx.Context(0) as c:
+        with pytest.raises(logfx.LogfxError):
+            c.gate_load(str(tmp_path / "absent.bin"))
+        bad = tmp_path / "bad.bin"
+        bad.write_bytes(b"LOGFXGT1" + b"\x00" * 7)
+        with pytest.raises(logfx.LogfxError):
+            c.gate_load(str(bad))
+        d = to_device(img)
+        out, rep = c.extract(d, logfx.Params(*lib_t, smooth=logfx.SMOOTH_GATE), bits=11, report=True)
+        ref = c.extract(d, logfx.Params(*lib_t, smooth=logfx.SMOOTH_ALWAYS), bits=11)
+        torch.cuda.synchronize()
+        assert rep["gate_fallback"] == 1 and rep["gated"] == 0 and rep["smoothed"] == 1
+        assert torch.equal(out, ref)
+
+
 def test_training_reduces_loss_deterministically(ctx):
     """Steps of backward + AdamW on a separable synthetic task: the loss
     falls, the accuracy rises, and two runs from the same start give the
