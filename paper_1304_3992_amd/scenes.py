@@ -206,12 +206,21 @@ def config5_base(size: int = 16384, seed: int = 5) -> np.ndarray:
                         noise_sigma=0.0, sp_density=0.0, bits=11)
 
 
-def config5_tile(base: np.ndarray, band: int, ty: int, tx: int, tile: int = 2048, seed: int = 5):
-    """(noisy, clean, sigma, density) of tile (ty, tx) of band `band`."""
+def config5_tile(base: np.ndarray, band: int, ty: int, tx: int, tile: int = 2048, seed: int = 5,
+                 per_band: bool = False):
+    """(noisy, clean, sigma, density) of tile (ty, tx) of band `band`.  By
+    default every (band, tile) draws its own sigma ~ U[0, 20] and density
+    ~ U[0, 0.2]; with per_band the band draws them once for all its tiles
+    (the noise of a band as a sensor gives it), and each tile still draws
+    its own noise values."""
     maxv = 2047
     rng = np.random.default_rng([seed, band, ty, tx])
     sigma = float(rng.uniform(0.0, 20.0))
     density = float(rng.uniform(0.0, 0.2))
+    if per_band:
+        brng = np.random.default_rng([seed, 1000 + band])
+        sigma = float(brng.uniform(0.0, 20.0))
+        density = float(brng.uniform(0.0, 0.2))
     b = base[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile].astype(np.float64)
     clean = np.clip(np.rint(C5_GAIN[band] * b + C5_OFFSET[band]), 0, maxv)
     return _noise(clean, rng, sigma, density, maxv), clean.astype(np.uint16), sigma, density

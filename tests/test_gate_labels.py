@@ -94,7 +94,8 @@ def _rule_from_fractions(d_raw, d_med, N):
 
 
 @pytest.mark.parametrize("name", ["gate_labels.npz", "gate_labels_2048.npz", "gate_labels_1024b.npz",
-                                  "gate_labels_scenes.npz", "config5_labels.npz"])
+                                  "gate_labels_scenes.npz", "config5_labels.npz",
+                                  "config5_perband_labels.npz"])
 def test_every_stored_label_follows_the_rule(name):
     d = np.load(os.path.join(GOLDEN, name))
     side = int(d["tile"]) if "tile" in d.files else int(d["size"])
@@ -148,19 +149,32 @@ def config5_base():
     return scenes.config5_base()
 
 
-def test_config5_labels_recomputed_and_inputs_unchanged(config5_base):
-    """The four-band benchmark's best-choice labels: the generated base
-    scene and tiles still hash to the stored values (so the stored labels
-    belong to the tiles the benchmark runs), and tiles relabelled by the
-    oracle give the stored fractions, labels and E/F difference counts."""
-    d = np.load(os.path.join(GOLDEN, "config5_labels.npz"))
+@pytest.mark.parametrize("name,per_band", [("config5_labels.npz", False), ("config5_perband_labels.npz", True)])
+def test_config5_labels_recomputed_and_inputs_unchanged(config5_base, name, per_band):
+    """The four-band benchmark's best-choice records (per-tile and per-band
+    noise): the generated base scene and tiles still hash to the stored
+    values (so the stored records belong to the tiles the benchmark runs),
+    and tiles relabelled by the oracle give the stored fractions, labels,
+    E/F difference counts, map hashes and network logits."""
+    d = np.load(os.path.join(GOLDEN, name))
     assert scenes.sha256(config5_base) == str(d["base_sha"])
+    assert bool(int(d["per_band"])) == per_band
+    weights = os.path.join(os.path.dirname(GOLDEN), "..", "paper_1304_3992_amd", "gate_weights.bin")
+    raw = open(weights, "rb").read()
+    assert scenes.sha256(np.frombuffer(raw, np.uint8)) == str(d["weights_sha"])
+    theta = np.frombuffer(raw[16:], "<f4").astype(np.float64)
     index = scenes.config5_index()
     assert len(index) == len(d["label"])
     taps = (oracle.log_mask(5, 0.8, 16)[0], oracle.log_mask(9, 1.4, 16)[0])
     picks = sorted({0, len(index) - 1, int(np.argmax(d["label"])), int(np.argmin(d["label"])), 77, 150})
     for i in picks:
         b, ty, tx = index[i]
-        noisy, clean, _, _ = scenes.config5_tile(config5_base, b, ty, tx)
+        noisy, clean, sigma, _ = scenes.config5_tile(config5_base, b, ty, tx, per_band=per_band)
         assert scenes.sha256(noisy) == str(d["sha"][i])
-        _check_row(d, i, gate.tile_label(noisy, clean, taps), ("d_raw", "d_med", "label", "diff"))
+        assert np.float64(sigma) == d["sigma"][i]
+        o = oracle.extract(noisy, taps[0], taps[1], smooth=True, want_intermediates=True)
+        c = oracle.extract(clean, taps[0], taps[1], smooth=False)
+        _check_row(d, i, gate.smoothing_label(o["E"], o["F"], c["F"]), ("d_raw", "d_med", "label", "diff"))
+        assert scenes.sha256(o["E"]) == str(d["sha_E"][i]) and scenes.sha256(o["F"]) == str(d["sha_F"][i])
+        z = gate.forward(theta, gate.features(noisy, o["Z1"], o["Z2"], 11)[None])[0][0]
+        assert float(z) == float(d["logit"][i])
