@@ -203,6 +203,25 @@ int logfx_check_params(const logfx_image *img, const logfx_params *p, int32_t *p
 int logfx_extract(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, uint8_t *out,
                   logfx_report *rep, void *stream);
 
+/* logfx_extract for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * The same pipeline and the same output bytes as logfx_extract; the call
+ * allocates nothing, host or device.  Its scratch (per-tile sums and counts
+ * of both passes, the image's statistics) is a fixed static array of 3.5
+ * MiB on each device, held until the process ends; pass 2 recomputes the
+ * crossing strengths (as LOGFX_OPT_STORE_Z = 0 does) instead of storing
+ * them.  The tile heights come from ctx's options; no report, no timing.
+ * Limits (LOGFX_EINVAL beyond them, before anything is enqueued): at most
+ * 65536 tiles per pass -- with the default 64-row strips about 0.94
+ * Gpixel, e.g. 30000 x 30000 -- and no std5_max >= 0, median_cascade,
+ * gate_region, nor LOGFX_SMOOTH_GATE with gate parameters loaded (GATE
+ * without parameters runs as ALWAYS).  Every call on a device shares that
+ * device's array: calls that overlap in time on one device (other streams,
+ * other contexts, other threads) race and give undefined output; calls
+ * ordered on one stream are safe.  Other behaviour as logfx_extract. */
+int logfx_extract_noalloc(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, uint8_t *out,
+                          void *stream);
+
 /* The first half of the pipeline alone, for inspection and testing: the two
  * LoG responses (Sec. 4.1) and the two crossing-strength maps (Sec. 3.2) as
  * FP64 maps in LoG response units.  Each output is a DEVICE array of

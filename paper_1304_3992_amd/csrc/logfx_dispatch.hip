@@ -2,6 +2,8 @@
 // instantiation units (one per pair of mask radii, logfx_kernels_inst.hip).
 #include "logfx_kernels.h"
 
+#include <mutex>
+
 #define LOGFX_RADII(X)                                                                            \
     X(1, 1) X(1, 2) X(2, 2) X(1, 3) X(2, 3) X(3, 3) X(1, 4) X(2, 4) X(3, 4) X(4, 4)
 
@@ -116,6 +118,26 @@ hipError_t launch_pass2_d(int ra, int rb, const Pass2Args<OrbitTapsD> &a, int gr
 #undef X
     return hipErrorInvalidValue;
 }
+// The scratch of logfx_extract_noalloc: every call on a device shares its
+// copy, which keeps the last call's contents (each pass writes every slot it
+// later reads, so nothing needs clearing).
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(kern::finalize_kernel, dim3(a.L.nimg), dim3(256), 0, s, a);
     return hipGetLastError();

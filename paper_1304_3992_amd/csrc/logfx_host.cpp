@@ -90,6 +90,10 @@ struct logfx_ctx {
     std::vector<char> timed_graph;   // per timed call: 1 if it was a graph replay
     int alloc_count = 0;
     int fail_alloc_at = -1;          // test hook: LOGFX_FAIL_ALLOC=n fails the n-th allocation
+    // device address of the static scratch of logfx_extract_noalloc on this
+    // context's device (looked up in logfx_create), or the lookup's error
+    void *noalloc = nullptr;
+    std::string noalloc_err;
     // smoothing gate: parameters, optimiser state and workspaces
     struct Gate {
         float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;   // [kNParam]
@@ -518,6 +522,24 @@ ImageDesc image_desc(const logfx_image *img) {
     return d;
 }
 
+// Image i of a launch: its descriptor, output, tiling, first tiles in the
+// launch's tile lists and first element in the strength map.
+ImageJob make_job(const logfx_image &img, const ImageTiles &t, uint8_t *out, long long zoff, int b1, int b2) {
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    j.zoff = zoff;
+    j.img = image_desc(&img);
+    j.out = out;
+    j.out_pitch = img.width;
+    j.tiles_x1 = t.tiles_x1;
+    j.tiles_x2 = t.tiles_x2;
+    j.ntiles1 = t.ntiles1;
+    j.ntiles2 = t.ntiles2;
+    j.base1 = b1;
+    j.base2 = b2;
+    return j;
+}
+
 // Everything one call enqueues.
 struct Call {
     Plan pl;
@@ -607,19 +629,8 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
     c.L.total2 = (int)t2;
     long long zoff = 0;
     auto job = [&](int i, int b1, int b2) {
-        ImageJob j;
-        std::memset(&j, 0, sizeof j);
-        j.zoff = zoff;
+        const ImageJob j = make_job(imgs[i], c.tiles[i], outs ? outs[i] : nullptr, zoff, b1, b2);
         zoff += imgs[i].height * imgs[i].width;
-        j.img = image_desc(&imgs[i]);
-        j.out = outs ? outs[i] : nullptr;
-        j.out_pitch = imgs[i].width;
-        j.tiles_x1 = c.tiles[i].tiles_x1;
-        j.tiles_x2 = c.tiles[i].tiles_x2;
-        j.ntiles1 = c.tiles[i].ntiles1;
-        j.ntiles2 = c.tiles[i].ntiles2;
-        j.base1 = b1;
-        j.base2 = b2;
         return j;
     };
     if (n == 1) {
@@ -1166,6 +1177,13 @@ int logfx_create(logfx_ctx **out, int device) {
     ctx->device = device;
     ctx->tiles = tile_cfg_from_env();
     if (const char *f = std::getenv("LOGFX_FAIL_ALLOC")) ctx->fail_alloc_at = std::atoi(f);
+    {   // the static scratch of logfx_extract_noalloc, with the device current
+        DeviceGuard g(device);
+        void *p = nullptr;
+        const hipError_t se = g.ok ? noalloc_scratch(device, &p) : hipErrorInvalidDevice;
+        if (se == hipSuccess) ctx->noalloc = p;
+        else ctx->noalloc_err = hipGetErrorString(se);
+    }
     *out = ctx;
     return LOGFX_OK;
 }
@@ -1261,6 +1279,61 @@ int logfx_extract(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p,
     if (!img) return set_err(ctx, LOGFX_EINVAL, "image is NULL");
     uint8_t *outs[1] = {out};
     return run(ctx, 1, img, p, outs, nullptr, nullptr, rep, stream);
+}
+
+int logfx_extract_noalloc(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, uint8_t *out,
+                          void *stream) {
+    if (!ctx) return set_err(nullptr, LOGFX_EINVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!img) return set_err(ctx, LOGFX_EINVAL, "image is NULL");
+    if (!out) return set_err(ctx, LOGFX_EINVAL, "output 0 is NULL");
+    Call c;   // c.tiles stays empty: this path allocates nothing, host or device
+    int rc = check_all(ctx, img, p, c.pl);
+    if (rc != LOGFX_OK) return rc;
+    if (c.pl.std5 || c.pl.ncas > 0 || c.pl.region > 0)
+        return set_err(ctx, LOGFX_EINVAL, "the 5x5 first stage, the median cascade and the per-region gate "
+                                          "need context memory (logfx_extract runs them)");
+    if (p->smooth == LOGFX_SMOOTH_GATE && ctx->gate.loaded)
+        return set_err(ctx, LOGFX_EINVAL, "the gate needs context memory (logfx_extract runs it)");
+    ImageTiles t;
+    if ((rc = tile_image(ctx, img, c.pl, false, t)) != LOGFX_OK) return rc;
+    if (t.ntiles1 > kNoAllocMaxTiles || t.ntiles2 > kNoAllocMaxTiles)
+        return set_err(ctx, LOGFX_EINVAL, "a %lld x %lld image needs %d pass-1 and %d pass-2 tiles; the static "
+                                          "scratch holds %lld per pass", (long long)img->height,
+                       (long long)img->width, t.ntiles1, t.ntiles2, kNoAllocMaxTiles);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
+    if (!ctx->noalloc)
+        return set_err(ctx, LOGFX_EDEVICE, "the static scratch of device %d is not available: %s", ctx->device,
+                       ctx->noalloc_err.c_str());
+    c.n = 1;
+    c.storez = false;
+    std::memset(&c.L, 0, sizeof c.L);
+    c.L.nimg = 1;
+    c.L.total1 = t.ntiles1;
+    c.L.total2 = t.ntiles2;
+    c.L.one = make_job(*img, t, out, 0, 0, 0);
+    Launches k;
+    if ((rc = build_launches(ctx, c, p, nullptr, nullptr, k, 0)) != LOGFX_OK) return rc;
+    // the sums, counts and statistics in the static array
+    unsigned char *base = static_cast<unsigned char *>(ctx->noalloc);
+    double *partials = reinterpret_cast<double *>(base + kNoAllocPartialsOff);
+    long long *counts1 = reinterpret_cast<long long *>(base + kNoAllocCounts1Off);
+    int *counts2 = reinterpret_cast<int *>(base + kNoAllocCounts2Off);
+    DevStats *stats = reinterpret_cast<DevStats *>(base + kNoAllocStatsOff);
+    if (k.path == LOGFX_PATH_INT32) {
+        k.p1.i.partials = partials, k.p1.i.counts = counts1;
+        k.p2.i.stats = stats, k.p2.i.counts = counts2;
+    } else {
+        k.p1.d.partials = partials, k.p1.d.counts = counts1;
+        k.p2.d.stats = stats, k.p2.d.counts = counts2;
+    }
+    k.fin.partials = partials;
+    k.fin.counts = counts1;
+    k.fin.stats = stats;
+    const hipError_t e = launch_all(k, (hipStream_t)stream, nullptr, UNTIL_OUTPUT);
+    if (e != hipSuccess) return hip_err(ctx, e, "kernel launch");
+    return LOGFX_OK;
 }
 
 int logfx_extract_batch(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_params *p,

@@ -187,6 +187,20 @@ hipError_t launch_pass2z_i(const Pass2Args<OrbitTapsI> &a, int grid, hipStream_t
 hipError_t launch_median_level(const LevelArgs &a, int halo, hipStream_t s);
 hipError_t launch_pass2z_d(const Pass2Args<OrbitTapsD> &a, int grid, hipStream_t s, int *max_grid = nullptr);
 
+// Static scratch of logfx_extract_noalloc (one array per device, in
+// logfx_dispatch.hip): the per-tile sums and counts of both passes and the
+// image's statistics, for at most kNoAllocMaxTiles tiles per pass.
+constexpr long long kNoAllocMaxTiles = 65536;
+constexpr size_t kNoAllocPartialsOff = 0;                                              // double [T][4]
+constexpr size_t kNoAllocCounts1Off = kNoAllocPartialsOff + kNoAllocMaxTiles * 4 * sizeof(double);  // i64 [T][2]
+constexpr size_t kNoAllocCounts2Off = kNoAllocCounts1Off + kNoAllocMaxTiles * 2 * sizeof(long long); // i32 [T][2]
+constexpr size_t kNoAllocStatsOff = kNoAllocCounts2Off + kNoAllocMaxTiles * 2 * sizeof(int);        // DevStats
+constexpr size_t kNoAllocBytes = (kNoAllocStatsOff + sizeof(DevStats) + 255) / 256 * 256;
+// Device address of that array on `device` (which must be the current
+// device), looked up once per device and kept; the array's host-side name is
+// not a device address.
+hipError_t noalloc_scratch(int device, void **ptr);
+
 // LDS bytes of one workgroup.
 inline size_t lds_bytes(int rows, int halo, int rb) {
     return (size_t)tile_lds_stride(halo, rb) * (rows + 2 * halo + 2 * rb) * sizeof(uint16_t);

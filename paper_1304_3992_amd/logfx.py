@@ -27,7 +27,8 @@ EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_set_option", "logfx_get_option", "logfx_tune",
            "logfx_gate_features", "logfx_gate_set_params", "logfx_gate_get_params",
            "logfx_gate_load", "logfx_gate_save", "logfx_gate_forward", "logfx_gate_backward",
-           "logfx_gate_step", "logfx_gate", "logfx_gate_save_state", "logfx_gate_load_state"]
+           "logfx_gate_step", "logfx_gate", "logfx_gate_save_state", "logfx_gate_load_state",
+           "logfx_extract_noalloc"]
 GATE_NPARAM, GATE_CELLS, GATE_MAX_BATCH = 14369, 128, 4096
 OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH, OPT_STORE_Z = 1, 2, 3, 4, 5
 ALLOW_INEXACT = 1
@@ -116,6 +117,8 @@ def load(path: str | None = None):
     lib.logfx_extract.restype = ctypes.c_int
     lib.logfx_extract.argtypes = [P, ctypes.POINTER(logfx_image), ctypes.POINTER(logfx_params), P,
                                   ctypes.POINTER(logfx_report), P]
+    lib.logfx_extract_noalloc.restype = ctypes.c_int
+    lib.logfx_extract_noalloc.argtypes = [P, ctypes.POINTER(logfx_image), ctypes.POINTER(logfx_params), P, P]
     lib.logfx_extract_maps.restype = ctypes.c_int
     lib.logfx_extract_maps.argtypes = [P, ctypes.POINTER(logfx_image),
                                        ctypes.POINTER(logfx_params), P, P, P, P, P]
@@ -293,6 +296,15 @@ class Context:
                                     _stream_ptr(stream))
         _check(rc, self.ptr)
         return (out, rep.as_dict()) if report else out
+
+    def extract_noalloc(self, img_t, params: Params, out, *, bits: int = 0, stream=None):
+        """logfx_extract_noalloc: the pipeline into the caller's uint8 map
+        `out` (same shape as the image) with no allocation in the library."""
+        img = image(img_t, bits)
+        rc = self.lib.logfx_extract_noalloc(self.ptr, ctypes.byref(img), ctypes.byref(params.c),
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        _check(rc, self.ptr)
+        return out
 
     def timing_enable(self, on: bool = True):
         _check(self.lib.logfx_timing_enable(self.ptr, int(bool(on))), self.ptr)
