@@ -47,50 +47,62 @@ struct Geo {
 // ---------------------------------------------------------------- forward
 // out[b][co][p] = bf16(relu(bias[co] + sum_{ci,ky,kx} w[co][ci][ky][kx] in[b][ci][2oy+ky-1][2ox+kx-1]))
 // for output pixel p = (oy, ox).  GEMM rows = co, columns = 16 pixels of one
-// image, reduction over (ci, ky, kx).
-template <int CI, int CO, int HI>
+// image, reduction over (ci, ky, kx).  A wave takes PW consecutive blocks of
+// 16 pixels of one image: each weight fragment is loaded once for the PW
+// products that use it.
+template <int CI, int CO, int HI, int PW>
 __global__ __launch_bounds__(256) void conv_fwd(const uint16_t *__restrict__ in, const int *__restrict__ idx,
                                                 const uint16_t *__restrict__ w, const float *__restrict__ bias,
                                                 uint16_t *__restrict__ out, int B) {
     using G = Geo<CI, CO, HI>;
-    constexpr int PB = G::HWO / 16;
+    constexpr int PB = G::HWO / 16;   // 16-pixel blocks per image
+    static_assert(PB % PW == 0, "whole blocks per wave");
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / 64);
-    if (wave >= B * PB) return;
-    const int b = wave / PB, p0 = (wave % PB) * 16;
+    if (wave >= B * (PB / PW)) return;
+    const int b = wave / (PB / PW), pb0 = (wave % (PB / PW)) * PW;
     const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
-    const int p = p0 + c, oy = p / G::HO, ox = p % G::HO;
     const uint16_t *ib = in + (long long)(idx ? idx[b] : b) * CI * G::HWI;
-    f32x4 acc[G::MB];
-#pragma unroll
-    for (int mb = 0; mb < G::MB; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < G::KP; kb += 16) {
-        bf16x4 bv;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = kb + 4 * q + i;
-            const int ci = k / 9, t = k - 9 * ci, ky = t / 3, kx = t - 3 * ky;
-            const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;   // < HI always
-            bv[i] = (k < G::K && iy >= 0 && ix >= 0) ? (short)ib[ci * G::HWI + iy * HI + ix] : (short)0;
-        }
-#pragma unroll
-        for (int mb = 0; mb < G::MB; ++mb) {
-            bf16x4 av;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = kb + 4 * q + i;
-                av[i] = k < G::K ? (short)w[(mb * 16 + c) * G::K + k] : (short)0;
-            }
-            acc[mb] = mfma(av, bv, acc[mb]);
-        }
-    }
+    f32x4 acc[G::MB][PW];
 #pragma unroll
     for (int mb = 0; mb < G::MB; ++mb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int co = mb * 16 + 4 * q + i;
-            out[((long long)b * CO + co) * G::HWO + p] = to_bf16(fmaxf(acc[mb][i] + bias[co], 0.0f));
+        for (int j = 0; j < PW; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < G::KP; kb += 16) {
+        bf16x4 av[G::MB];
+#pragma unroll
+        for (int mb = 0; mb < G::MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = kb + 4 * q + i;
+                av[mb][i] = k < G::K ? (short)w[(mb * 16 + c) * G::K + k] : (short)0;
+            }
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const int p = (pb0 + j) * 16 + c, oy = p / G::HO, ox = p % G::HO;
+            bf16x4 bv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = kb + 4 * q + i;
+                const int ci = k / 9, t = k - 9 * ci, ky = t / 3, kx = t - 3 * ky;
+                const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;   // < HI always
+                bv[i] = (k < G::K && iy >= 0 && ix >= 0) ? (short)ib[ci * G::HWI + iy * HI + ix] : (short)0;
+            }
+#pragma unroll
+            for (int mb = 0; mb < G::MB; ++mb) acc[mb][j] = mfma(av[mb], bv, acc[mb][j]);
         }
+    }
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+        const int p = (pb0 + j) * 16 + c;
+#pragma unroll
+        for (int mb = 0; mb < G::MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = mb * 16 + 4 * q + i;
+                out[((long long)b * CO + co) * G::HWO + p] = to_bf16(fmaxf(acc[mb][j][i] + bias[co], 0.0f));
+            }
+    }
 }
 
 // gap[b][c] = mean of a3[b][c]; z[b] = sum_c gap[b][c] wf[c] + bf
@@ -339,12 +351,12 @@ __global__ __launch_bounds__(256) void decide(const float *logits, int *flags, u
 
 inline unsigned blocks(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <int CI, int CO, int HI>
+template <int CI, int CO, int HI, int PW>
 hipError_t fwd(const uint16_t *in, const int *idx, const uint16_t *w, const float *bias, uint16_t *out, int B,
                hipStream_t s) {
     using G = Geo<CI, CO, HI>;
-    hipLaunchKernelGGL((conv_fwd<CI, CO, HI>), dim3(blocks((long long)B * (G::HWO / 16), 4)), dim3(256), 0, s, in,
-                       idx, w, bias, out, B);
+    hipLaunchKernelGGL((conv_fwd<CI, CO, HI, PW>), dim3(blocks((long long)B * (G::HWO / 16 / PW), 4)), dim3(256), 0, s,
+                       in, idx, w, bias, out, B);
     return hipGetLastError();
 }
 
@@ -393,9 +405,9 @@ hipError_t launch_finish_features(const Launch &L, const unsigned long long *cel
 
 hipError_t launch_forward(const NetBuffers &n, hipStream_t s) {
     hipError_t e;
-    if ((e = fwd<kC0, kC1, kH0>(n.x0, n.idx, n.w + kOffW1, n.theta + kOffB1, n.a1, n.B, s)) != hipSuccess) return e;
-    if ((e = fwd<kC1, kC2, kH1>(n.a1, nullptr, n.w + kOffW2, n.theta + kOffB2, n.a2, n.B, s)) != hipSuccess) return e;
-    if ((e = fwd<kC2, kC3, kH2>(n.a2, nullptr, n.w + kOffW3, n.theta + kOffB3, n.a3, n.B, s)) != hipSuccess) return e;
+    if ((e = fwd<kC0, kC1, kH0, 4>(n.x0, n.idx, n.w + kOffW1, n.theta + kOffB1, n.a1, n.B, s)) != hipSuccess) return e;
+    if ((e = fwd<kC1, kC2, kH1, 4>(n.a1, nullptr, n.w + kOffW2, n.theta + kOffB2, n.a2, n.B, s)) != hipSuccess) return e;
+    if ((e = fwd<kC2, kC3, kH2, 2>(n.a2, nullptr, n.w + kOffW3, n.theta + kOffB3, n.a3, n.B, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(head_fwd, dim3(n.B), dim3(64), 0, s, n.a3, n.theta, n.gap, n.logits);
     return hipGetLastError();
 }
