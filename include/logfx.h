@@ -25,6 +25,11 @@
  *     padding of Sec. 4.1, whose values the paper does not give).
  *   - A context owns device scratch memory and is used by one host thread
  *     at a time; calls on one context are ordered by the caller's streams.
+ *   - Environment: LOGFX_LOG=1 writes one line per call and every error to
+ *     stderr; LOGFX_TUNE_CACHE names the autotuner's cache file when
+ *     logfx_tune is given none; LOGFX_TILE="rows1,rows2" sets a new
+ *     context's strip heights; LOGFX_FAIL_ALLOC=n makes the n-th device
+ *     allocation of a new context fail (a test hook).
  */
 #ifndef LOGFX_H
 #define LOGFX_H
@@ -276,7 +281,7 @@ int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value);
  * JSON lines keyed by device architecture, arithmetic path, mask radii,
  * pixel type, smoothing and batch/single; an entry found there is applied
  * without measuring, a new result is appended.  res (nullable) receives the
- * choice. */
+ * choice.  cache_path NULL: the file LOGFX_TUNE_CACHE names, if set. */
 typedef struct {
     int32_t rows1, rows2, persistent;
     int32_t from_cache;   /* 1 if taken from the cache file */

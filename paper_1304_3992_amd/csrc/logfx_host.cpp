@@ -72,10 +72,20 @@ struct logfx_ctx {
     DevStats *h_stats = nullptr;
     int *h_counts2 = nullptr;
     long long h_capn = 0, h_cap2 = 0;
-    ImageJob *h_jobs = nullptr;
-    int *h_owner1 = nullptr, *h_owner2 = nullptr;
-    long long h_tcapn = 0, h_tcap1 = 0, h_tcap2 = 0;
-    hipEvent_t staged = nullptr;     // last upload of the staging buffers
+    // batch tables: two pinned staging sets used in turn (a set is rewritten
+    // only after the upload from it, two uploads back, has finished), and the
+    // tables the device buffers hold, so that an unchanged batch uploads
+    // nothing
+    struct Staging {
+        ImageJob *jobs = nullptr;
+        int *own1 = nullptr, *own2 = nullptr;
+        long long capn = 0, cap1 = 0, cap2 = 0;
+        hipEvent_t done = nullptr;   // the last upload from this set
+    } stage[2];
+    int stage_next = 0;
+    std::vector<ImageJob> tab_jobs;
+    std::vector<int> tab_own1, tab_own2;
+    bool tab_valid = false;          // jobs / owner1 / owner2 hold tab_*
     // captured batch graph and the launch arguments it was captured with
     hipStream_t capture = nullptr;
     hipGraph_t g = nullptr;
@@ -116,6 +126,25 @@ struct logfx_ctx {
 
 namespace {
 
+// LOGFX_LOG=1 (read once): one line per call and every error on stderr.
+bool log_on() {
+    static const bool on = [] {
+        const char *v = std::getenv("LOGFX_LOG");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void log_line(const char *fmt, ...) {
+    if (!log_on()) return;
+    char buf[768];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[liblogfx] %s\n", buf);
+}
+
 int set_err(logfx_ctx *ctx, int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -124,6 +153,7 @@ int set_err(logfx_ctx *ctx, int code, const char *fmt, ...) {
     va_end(ap);
     if (ctx) ctx->err = buf;
     else g_thread_error = buf;
+    log_line("error %d: %s", code, buf);
     return code;
 }
 
@@ -171,6 +201,7 @@ int realloc_dev(logfx_ctx *ctx, T *&p, long long count) {
 // nimg images.
 int ensure_scratch(logfx_ctx *ctx, long long n1, long long n2, long long nimg) {
     int rc;
+    if (n1 > ctx->cap1 || n2 > ctx->cap2 || nimg > ctx->capn) ctx->tab_valid = false;
     if (n1 > ctx->cap1) {
         ctx->cap1 = 0;
         if ((rc = realloc_dev(ctx, ctx->partials, n1 * 4)) != LOGFX_OK ||
@@ -485,8 +516,9 @@ struct ImageTiles {
     int tiles_x1, ntiles1, tiles_x2, ntiles2;
 };
 
-int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, bool storez, ImageTiles &t) {
-    const TileCfg &c = ctx->tiles;
+int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, bool storez, int rows1, ImageTiles &t) {
+    TileCfg c = ctx->tiles;
+    c.rows1 = rows1;
     const long long H = img->height, W = img->width;
     if (H >= (1LL << 30) || W >= (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image sides must be below 2^30");
@@ -546,8 +578,28 @@ struct Call {
     Launch L;
     int n = 1;
     bool storez = false;   // pass 1 stores the strengths in ctx->zmap, pass 2 reads them
+    int rows1 = 64;        // pass-1 strip height of this call
+    int cell_slots = 0, cell_rows = 0;   // LDS slots of pass 1's gate cell sums per tile
     std::vector<ImageTiles> tiles;
 };
+
+// LDS slots of the gate's per-tile cell sums for pass-1 strips of `rows`
+// rows.  A tile's slot of cell (cy, cx) is (cy - its first cell row) x slots
+// + (cx - its first cell column), so the slots must cover the span of cell
+// indices one tile of tile_out_width(kHalo1) columns and `rows` rows reaches
+// in any image -- with CX x CY cells across (kGateCells per region side),
+// floor((n - 1) CX / W) + 2 columns for n columns, at most CX (images
+// narrower than CX have empty cells between their columns' cells).
+void cell_layout(int n, const logfx_image *imgs, const Plan &pl, int rows, long long &slots, long long &crows) {
+    const long long CX = (long long)kGateCells * pl.gx, CY = (long long)kGateCells * pl.gy;
+    const long long TW = tile_out_width(kHalo1);
+    slots = crows = 1;
+    for (int i = 0; i < n; ++i) {
+        const long long W = imgs[i].width, H = imgs[i].height;
+        slots = std::max(slots, std::min(CX, (TW - 1) * CX / W + 2));
+        crows = std::max(crows, std::min(CY, (rows - 1) * CY / H + 2));
+    }
+}
 
 // Device memory for the strength pairs of `px` pixels; false if it cannot
 // be had (the call then recomputes the strengths in pass 2).
@@ -569,10 +621,25 @@ bool ensure_zmap(logfx_ctx *ctx, long long px, int path) {
 // Validates the images against the parameters, tiles them and (for a batch)
 // uploads the image table and tile owners.
 int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p,
-            uint8_t *const *outs, bool need_out, Call &c, hipStream_t s) {
+            uint8_t *const *outs, bool need_out, bool features, Call &c, hipStream_t s) {
     if (n < 1 || !imgs) return set_err(ctx, LOGFX_EINVAL, "no images");
     int rc = check_all(ctx, &imgs[0], p, c.pl);
     if (rc != LOGFX_OK) return rc;
+    c.rows1 = ctx->tiles.rows1;
+    if (features) {
+        // pass 1 keeps a slot per (cell row, cell column) a tile spans in
+        // LDS beside the tile: lower the strip height where they would not
+        // fit in 64 KiB together (only images of a few hundred pixels with
+        // cells of a pixel or two come near it)
+        long long slots = 1, crows = 1;
+        for (; c.rows1 > 1; --c.rows1) {
+            cell_layout(n, imgs, c.pl, c.rows1, slots, crows);
+            if (lds_bytes(c.rows1, kHalo1, c.pl.rb) + 2 * sizeof(unsigned) * slots * crows <= 65536) break;
+        }
+        cell_layout(n, imgs, c.pl, c.rows1, slots, crows);
+        c.cell_slots = (int)slots;
+        c.cell_rows = (int)crows;
+    }
     if (n > 1 && c.pl.region > 0) return set_err(ctx, LOGFX_EINVAL, "gate_region applies to single-image calls");
     // strengths are stored between the passes when the context allows it and
     // the memory for them can be had; the 5x5 first stage and the median
@@ -616,7 +683,7 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
                                                   "dtype and bits", i);
         }
         if (need_out && (!outs || !outs[i])) return set_err(ctx, LOGFX_EINVAL, "output %d is NULL", i);
-        if ((rc = tile_image(ctx, &imgs[i], c.pl, c.storez, c.tiles[i])) != LOGFX_OK) return rc;
+        if ((rc = tile_image(ctx, &imgs[i], c.pl, c.storez, c.rows1, c.tiles[i])) != LOGFX_OK) return rc;
         t1 += c.tiles[i].ntiles1;
         t2 += c.tiles[i].ntiles2;
     }
@@ -637,33 +704,45 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
         c.L.one = job(0, 0, 0);
         return LOGFX_OK;
     }
-    // batch: stage the tables in pinned memory (after the previous upload
-    // from it has finished) and upload them on the call's stream
-    if (ctx->staged && (rc = hipEventSynchronize(ctx->staged)) != hipSuccess)
-        return hip_err(ctx, (hipError_t)rc, "hipEventSynchronize");
-    if ((rc = grow_host(ctx, ctx->h_jobs, ctx->h_tcapn, n)) != LOGFX_OK ||
-        (rc = grow_host(ctx, ctx->h_owner1, ctx->h_tcap1, t1)) != LOGFX_OK ||
-        (rc = grow_host(ctx, ctx->h_owner2, ctx->h_tcap2, t2)) != LOGFX_OK)
-        return rc;
+    // batch: the image table and the tile owners; uploaded on the call's
+    // stream only when they differ from what the device buffers hold
+    std::vector<ImageJob> jobs((size_t)n);
+    std::vector<int> own1((size_t)t1), own2((size_t)t2);
     int b1 = 0, b2 = 0;
     for (int i = 0; i < n; ++i) {
-        ctx->h_jobs[i] = job(i, b1, b2);
-        for (int k = 0; k < c.tiles[i].ntiles1; ++k) ctx->h_owner1[b1 + k] = i;
-        for (int k = 0; k < c.tiles[i].ntiles2; ++k) ctx->h_owner2[b2 + k] = i;
+        jobs[i] = job(i, b1, b2);
+        for (int k = 0; k < c.tiles[i].ntiles1; ++k) own1[b1 + k] = i;
+        for (int k = 0; k < c.tiles[i].ntiles2; ++k) own2[b2 + k] = i;
         b1 += c.tiles[i].ntiles1;
         b2 += c.tiles[i].ntiles2;
     }
-    hipError_t e;
-    if ((e = hipMemcpyAsync(ctx->jobs, ctx->h_jobs, sizeof(ImageJob) * n, hipMemcpyHostToDevice, s)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(ctx->owner1, ctx->h_owner1, sizeof(int) * t1, hipMemcpyHostToDevice, s)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(ctx->owner2, ctx->h_owner2, sizeof(int) * t2, hipMemcpyHostToDevice, s)) !=
-            hipSuccess)
-        return hip_err(ctx, e, "table upload");
-    if (!ctx->staged && (e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming)) != hipSuccess)
-        return hip_err(ctx, e, "hipEventCreate");
-    if ((e = hipEventRecord(ctx->staged, s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
+    const bool same = ctx->tab_valid && ctx->tab_jobs.size() == jobs.size() && ctx->tab_own1 == own1 &&
+                      ctx->tab_own2 == own2 &&
+                      std::memcmp(ctx->tab_jobs.data(), jobs.data(), sizeof(ImageJob) * jobs.size()) == 0;
+    if (!same) {
+        auto &S = ctx->stage[ctx->stage_next];
+        hipError_t e;
+        if (S.done && (e = hipEventSynchronize(S.done)) != hipSuccess) return hip_err(ctx, e, "hipEventSynchronize");
+        if ((rc = grow_host(ctx, S.jobs, S.capn, n)) != LOGFX_OK || (rc = grow_host(ctx, S.own1, S.cap1, t1)) != LOGFX_OK ||
+            (rc = grow_host(ctx, S.own2, S.cap2, t2)) != LOGFX_OK)
+            return rc;
+        std::memcpy(S.jobs, jobs.data(), sizeof(ImageJob) * n);
+        std::memcpy(S.own1, own1.data(), sizeof(int) * t1);
+        std::memcpy(S.own2, own2.data(), sizeof(int) * t2);
+        ctx->tab_valid = false;
+        if ((e = hipMemcpyAsync(ctx->jobs, S.jobs, sizeof(ImageJob) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ctx->owner1, S.own1, sizeof(int) * t1, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ctx->owner2, S.own2, sizeof(int) * t2, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_err(ctx, e, "table upload");
+        if (!S.done && (e = hipEventCreateWithFlags(&S.done, hipEventDisableTiming)) != hipSuccess)
+            return hip_err(ctx, e, "hipEventCreate");
+        if ((e = hipEventRecord(S.done, s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
+        ctx->stage_next ^= 1;
+        ctx->tab_jobs.swap(jobs);
+        ctx->tab_own1.swap(own1);
+        ctx->tab_own2.swap(own2);
+        ctx->tab_valid = true;
+    }
     c.L.jobs = ctx->jobs;
     c.L.owner1 = ctx->owner1;
     c.L.owner2 = ctx->owner2;
@@ -726,7 +805,7 @@ void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *con
         a1.dbgZ[slot] = Z ? Z[u] : nullptr;
         dbg = dbg || a1.dbgL[slot] || a1.dbgZ[slot];
     }
-    a1.rows = ctx->tiles.rows1;
+    a1.rows = c.rows1;
     a1.partials = ctx->partials;
     a1.counts = ctx->counts1;
     a2.rows = ctx->tiles.rows2;
@@ -814,8 +893,10 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
         k.cells = G.cells;
         k.feats = feats ? feats : G.feats;
         k.maxval = c.pl.maxpix;
-        if (k.path == LOGFX_PATH_INT32) k.p1.i.cells = G.cells;
-        else k.p1.d.cells = G.cells;
+        if (k.path == LOGFX_PATH_INT32)
+            k.p1.i.cells = G.cells, k.p1.i.cell_slots = c.cell_slots, k.p1.i.cell_rows = c.cell_rows;
+        else
+            k.p1.d.cells = G.cells, k.p1.d.cell_slots = c.cell_slots, k.p1.d.cell_rows = c.cell_rows;
         if (gate > 1) {
             if ((rc = ensure_gate_batch(ctx, k.nsets)) != LOGFX_OK) return rc;
             k.gated = true;
@@ -939,7 +1020,7 @@ int fill_reports(logfx_ctx *ctx, const Call &c, const logfx_params *p, const Lau
     for (int i = 0; i < c.n; ++i) {
         logfx_report &r = reps[i];
         std::memset(&r, 0, sizeof r);
-        const ImageJob &j = c.n == 1 ? c.L.one : ctx->h_jobs[i];
+        const ImageJob &j = c.n == 1 ? c.L.one : ctx->tab_jobs[i];
         r.pixels = j.img.H * j.img.W;
         for (int slot = 0; slot < 2; ++slot) {
             const int u = c.pl.order[slot];
@@ -981,14 +1062,20 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
     if (!dg.ok) return set_err(ctx, LOGFX_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t s = (hipStream_t)stream;
     Call c;
-    int rc = prepare(ctx, n, imgs, p, outs, !maps, c, s);
-    if (rc != LOGFX_OK) return rc;
     const bool gated = !maps && p->smooth == LOGFX_SMOOTH_GATE && ctx->gate.loaded;
+    int rc = prepare(ctx, n, imgs, p, outs, !maps, gated, c, s);
+    if (rc != LOGFX_OK) return rc;
     if (gated && (rc = check_cells(ctx, n, imgs, c.pl)) != LOGFX_OK) return rc;
     Launches k;
     if ((rc = build_launches(ctx, c, p, maps_L, maps_Z, k, gated ? 2 : 0)) != LOGFX_OK) return rc;
     hipError_t e;
     const bool use_graph = n > 1 && ctx->graph && !maps;
+    if (log_on())
+        log_line("%s: %d image(s), first %lld x %lld, %s path, radii %d/%d, tiles %d/%d (rows %d/%d), %s, smooth %d%s%s",
+             maps ? "extract_maps" : (n > 1 ? "extract_batch" : "extract"), n, (long long)imgs[0].height,
+             (long long)imgs[0].width, c.pl.path == LOGFX_PATH_INT32 ? "int32" : "fp64", c.pl.ra, c.pl.rb,
+             c.L.total1, c.L.total2, c.rows1, ctx->tiles.rows2, c.storez ? "stored strengths" : "recomputed strengths",
+             p->smooth, gated ? " (gated)" : "", use_graph ? ", graph" : "");
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     const bool timed = ctx->timing && !maps;
     if (timed) {
@@ -1023,7 +1110,7 @@ int run_gate(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params 
     if (until == UNTIL_FEATURES && !feats) return set_err(ctx, LOGFX_EINVAL, "feats is NULL");
     hipStream_t s = (hipStream_t)stream;
     Call c;
-    int rc = prepare(ctx, n, imgs, p, nullptr, false, c, s);
+    int rc = prepare(ctx, n, imgs, p, nullptr, false, true, c, s);
     if (rc != LOGFX_OK) return rc;
     if ((rc = check_cells(ctx, n, imgs, c.pl)) != LOGFX_OK) return rc;
     Launches k;
@@ -1195,9 +1282,14 @@ int logfx_destroy(logfx_ctx *ctx) {
         if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
         if (ctx->g) (void)hipGraphDestroy(ctx->g);
         if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
-        if (ctx->staged) {
-            (void)hipEventSynchronize(ctx->staged);
-            (void)hipEventDestroy(ctx->staged);
+        for (auto &S : ctx->stage) {
+            if (S.done) {
+                (void)hipEventSynchronize(S.done);
+                (void)hipEventDestroy(S.done);
+            }
+            if (S.jobs) (void)hipHostFree(S.jobs);
+            if (S.own1) (void)hipHostFree(S.own1);
+            if (S.own2) (void)hipHostFree(S.own2);
         }
         (void)hipFree(ctx->zmap);
         (void)hipFree(ctx->cmap);
@@ -1210,9 +1302,6 @@ int logfx_destroy(logfx_ctx *ctx) {
         (void)hipFree(ctx->owner2);
         if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
         if (ctx->h_counts2) (void)hipHostFree(ctx->h_counts2);
-        if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
-        if (ctx->h_owner1) (void)hipHostFree(ctx->h_owner1);
-        if (ctx->h_owner2) (void)hipHostFree(ctx->h_owner2);
         for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
         auto &G = ctx->gate;
         for (void *q : {(void *)G.theta, (void *)G.m, (void *)G.v, (void *)G.grad, (void *)G.wbf, (void *)G.act,
@@ -1288,6 +1377,7 @@ int logfx_extract_noalloc(logfx_ctx *ctx, const logfx_image *img, const logfx_pa
     if (!img) return set_err(ctx, LOGFX_EINVAL, "image is NULL");
     if (!out) return set_err(ctx, LOGFX_EINVAL, "output 0 is NULL");
     Call c;   // c.tiles stays empty: this path allocates nothing, host or device
+    c.rows1 = ctx->tiles.rows1;
     int rc = check_all(ctx, img, p, c.pl);
     if (rc != LOGFX_OK) return rc;
     if (c.pl.std5 || c.pl.ncas > 0 || c.pl.region > 0)
@@ -1296,7 +1386,7 @@ int logfx_extract_noalloc(logfx_ctx *ctx, const logfx_image *img, const logfx_pa
     if (p->smooth == LOGFX_SMOOTH_GATE && ctx->gate.loaded)
         return set_err(ctx, LOGFX_EINVAL, "the gate needs context memory (logfx_extract runs it)");
     ImageTiles t;
-    if ((rc = tile_image(ctx, img, c.pl, false, t)) != LOGFX_OK) return rc;
+    if ((rc = tile_image(ctx, img, c.pl, false, ctx->tiles.rows1, t)) != LOGFX_OK) return rc;
     if (t.ntiles1 > kNoAllocMaxTiles || t.ntiles2 > kNoAllocMaxTiles)
         return set_err(ctx, LOGFX_EINVAL, "a %lld x %lld image needs %d pass-1 and %d pass-2 tiles; the static "
                                           "scratch holds %lld per pass", (long long)img->height,
@@ -1613,11 +1703,13 @@ int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_p
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ctx->device);
     Call c;
-    int rc = prepare(ctx, n, imgs, p, outs, true, c, s);
+    int rc = prepare(ctx, n, imgs, p, outs, true, p && p->smooth == LOGFX_SMOOTH_GATE && ctx->gate.loaded, c, s);
     if (rc != LOGFX_OK) return rc;
     const std::string key = tune_key(ctx, c, p, &imgs[0]);
     logfx_tune_result best;
     std::memset(&best, 0, sizeof best);
+    if (!cache_path) cache_path = std::getenv("LOGFX_TUNE_CACHE");   // may stay NULL
+    if (cache_path && !*cache_path) cache_path = nullptr;
     if (cache_path && cache_lookup(cache_path, key, best)) {
         best.from_cache = 1;
     } else {

@@ -118,6 +118,10 @@ struct Pass1Args {
     // decides per region of a single image).
     unsigned long long *cells;
     int cells_lx, cells_ly;
+    // LDS slots of the per-tile cell sums (kP1Cells): cell_rows x cell_slots,
+    // at least the cell rows and the cell columns any tile of the launch
+    // spans.
+    int cell_slots, cell_rows;
 };
 
 template <class Taps>

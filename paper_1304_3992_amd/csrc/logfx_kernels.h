@@ -308,14 +308,29 @@ struct Strip {
                 }
             }
         } else {
-            const int w = threadIdx.x / kWave, nw = nt / kWave;
-            for (int r = w; r < RH; r += nw) {
-                const long long row = (long long)min(max(ry0 + r, 0), H - 1) * pitch;
-                uint16_t *dst = lds + r * stride;
-                for (int c = lane; c < stride; c += kWave) {
-                    const long long at = row + min(max(rx0 + c, 0), W - 1);
-                    dst[c] = img.dtype == 1 ? ((const uint16_t *)img.data)[at]
-                                            : (uint16_t)((const uint8_t *)img.data)[at];
+            // tiles at the left or right border, and images whose rows are
+            // not 8-pixel aligned: pixel by pixel with clamped coordinates,
+            // consecutive threads on consecutive columns (coalesced), eight
+            // loads in flight per thread before their LDS writes
+            typedef __attribute__((address_space(1))) const uint16_t GU16;
+            typedef __attribute__((address_space(1))) const uint8_t GU8;
+            const int npx = RH * stride;
+            for (int b = 0; b < npx; b += 8 * nt) {
+                uint16_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = b + k * nt + (int)threadIdx.x;
+                    if (i < npx) {
+                        const int row = i / stride, col = i - row * stride;
+                        const long long at = (long long)min(max(ry0 + row, 0), H - 1) * pitch +
+                                             min(max(rx0 + col, 0), W - 1);
+                        v[k] = img.dtype == 1 ? ((GU16 *)img.data)[at] : (uint16_t)((GU8 *)img.data)[at];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = b + k * nt + (int)threadIdx.x;
+                    if (i < npx) lds[i] = v[k];
                 }
             }
         }
@@ -401,10 +416,15 @@ template <> struct ZStore<double> {
 // outstanding vector memory operation, the strength stores included, and
 // measured slower than the lower occupancy.
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
+#ifndef LOGFX_P1_CELL_WAVES
+#define LOGFX_P1_CELL_WAVES 3
+#endif
 template <class Acc, int MODE, bool LOOP>
 constexpr int kPass1Waves =
-    (std::is_same<Acc, int>::value && ((MODE & kP1Cells) != 0 || ((MODE & kP1StoreZ) != 0 && LOOP))) ? 3
-                                                                                                   : kMinWaves<Acc>;
+    !std::is_same<Acc, int>::value ? kMinWaves<Acc>
+    : (MODE & kP1Cells) != 0       ? LOGFX_P1_CELL_WAVES
+    : ((MODE & kP1StoreZ) != 0 && LOOP) ? 3
+                                        : kMinWaves<Acc>;
 
 // MODE, a set of bits: 0 = statistics only; kP1Maps = also the FP64 maps
 // of a single image; kP1Cells = also the per-cell sums of the gate
@@ -415,10 +435,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     extern __shared__ uint16_t lds[];
     __shared__ double red[4][8];
     __shared__ long long redc[2][8];
-    // cell sums of the current cell row, one slot per cell column the tile
-    // touches (at most its 248 output columns)
-    __shared__ unsigned cellv[(MODE & kP1Cells) != 0 ? tile_out_width(kHalo1) : 1];
-    __shared__ unsigned cellc[(MODE & kP1Cells) != 0 ? tile_out_width(kHalo1) : 1];
+    // cell sums of the current cell row, one slot per cell column a tile
+    // touches (a.cell_slots of them), in the dynamic LDS after the tile: a
+    // fixed array for the worst case (248 one-pixel cells) would push the
+    // workgroup past a quarter of the CU's LDS
+    unsigned *const cellv = reinterpret_cast<unsigned *>(lds + Strip<kHalo1, RB>::stride * (a.rows + 2 * kHalo1 + 2 * RB));
+    unsigned *const cellc = cellv + a.cell_rows * a.cell_slots;
     constexpr int HL = kHalo1, P = 2 * RB + 1;
     // The step schedule below takes one halo row above and below the strip:
     // the crossing row r = t - 1 is an output row from the third step to the
@@ -431,7 +453,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     const Strip<HL, RB> g(J.img, item - J.base1, J.tiles_x1, a.rows);
     g.fill(lds, J.img);
     if constexpr ((MODE & kP1Cells) != 0) {
-        if (threadIdx.x < Strip<HL, RB>::TW) cellv[threadIdx.x] = cellc[threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < a.cell_rows * a.cell_slots; i += blockDim.x) cellv[i] = cellc[i] = 0;
     }
     __syncthreads();
 
@@ -450,16 +472,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     // x * CX / W)).
     // Each lane sums its pixel values and crossing indicators down its
     // column while the rows stay in one cell row.  At the end of a cell row
-    // (or of the strip) -- a row boundary that every wave of the workgroup
-    // reaches at the same step -- the lanes add their sums into the tile's
-    // LDS slot of their cell, and after a barrier one thread per slot adds
-    // the slot to the image's cell counters (integer atomics, exact).
+    // (or of the strip) the lanes add their sums into the tile's LDS slot of
+    // that cell -- one slot per (cell row, cell column) the tile spans, so no
+    // slot is reused within the tile and the row loop needs no barrier.
+    // After the last row one thread per slot adds the slot to the image's
+    // cell counters (integer atomics: exact and order-free).
     unsigned fv = 0, fc = 0;    // value sum; crossings of mask 1 + 2^16 * of mask 2
-    int fcy = 0;                // current cell row
+    int fcy = 0, fcy0 = 0;      // current cell row; the tile's first
+    int fspan = 0;              // cell rows from the tile's first to its last
     int fkey0 = 0, fslots = 0;  // the tile's first cell column and its number of cell columns
-    int fslot = 0;              // the LDS slot of the lane's cell column (output lanes)
+    int fslot = 0;              // the slot of the lane's cell column (output lanes)
     long long fnext = 0;        // first row of the next cell row
-    unsigned long long *fcells = nullptr;
     if constexpr ((MODE & kP1Cells) != 0) {
         // floor(n * cells / d) in FP64: exact, since n * cells < 2^53 and a
         // non-integer quotient lies at least 1/d from an integer
@@ -468,27 +491,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         fkey0 = cell_of(g.x0, CX, g.W);
         fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, CX, g.W) - fkey0 + 1;
         fslot = g.outc ? cell_of(g.xc, CX, g.W) - fkey0 : 0;
-        fcy = cell_of(g.y0, CY, g.H);
+        fcy = fcy0 = cell_of(g.y0, CY, g.H);
+        fspan = cell_of(g.y0 + g.Rv - 1, CY, g.H) - fcy0 + 1;
         fnext = (((long long)fcy + 1) * g.H + CY - 1) >> a.cells_ly;
-        fcells = a.cells + ((long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) << (a.cells_lx + a.cells_ly + 1));
     }
     auto flush = [&](const int r) __attribute__((always_inline)) {
         if (g.outc && (fv | fc)) {
-            atomicAdd(&cellv[fslot], fv);
-            atomicAdd(&cellc[fslot], fc);
+            const int at = (fcy - fcy0) * a.cell_slots + fslot;
+            atomicAdd(&cellv[at], fv);
+            atomicAdd(&cellc[at], fc);
         }
-        __syncthreads();
-        if ((int)threadIdx.x < fslots) {
-            const unsigned v = cellv[threadIdx.x], c = cellc[threadIdx.x];
-            if (v | c) {
-                unsigned long long *cell = fcells + ((long long)fcy << a.cells_lx) + fkey0 + threadIdx.x;
-                atomicAdd(cell, (unsigned long long)v);
-                atomicAdd(cell + (1ll << (a.cells_lx + a.cells_ly)),
-                          (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
-                cellv[threadIdx.x] = cellc[threadIdx.x] = 0;
-            }
-        }
-        __syncthreads();
         fv = fc = 0;
         // the cell row of row r + 1 (cells may be empty when H < cells):
         // the first c > fcy whose rows reach past r, by shifts only
@@ -566,6 +578,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     const bool inner_x = g.x0 - HL >= 1 && g.x0 + Strip<HL, RB>::TW + HL <= g.W - 1;
     if (inner_x && t0 >= 1 && t0 + nsteps - 1 <= g.H - 1) run(bool_c<false>{});
     else run(bool_c<true>{});
+
+    if constexpr ((MODE & kP1Cells) != 0) {
+        // the tile's cell slots into the image's counters, one thread per slot
+        __syncthreads();
+        unsigned long long *fcells =
+            a.cells + ((long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) << (a.cells_lx + a.cells_ly + 1));
+        for (int i = threadIdx.x; i < fspan * fslots; i += blockDim.x) {
+            const int cr = i / fslots, cc = i - cr * fslots;
+            const unsigned v = cellv[cr * a.cell_slots + cc];
+            const unsigned c = cellc[cr * a.cell_slots + cc];
+            if (v | c) {
+                unsigned long long *cell = fcells + ((long long)(fcy0 + cr) << a.cells_lx) + fkey0 + cc;
+                atomicAdd(cell, (unsigned long long)v);
+                atomicAdd(cell + (1ll << (a.cells_lx + a.cells_ly)),
+                          (unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32));
+            }
+        }
+    }
 
     // Deterministic per-tile reduction: fixed butterfly per wave, then the
     // waves in order.
@@ -741,7 +771,8 @@ hipError_t occupancy(K k, size_t shm, int *max_grid) {
 
 template <class Acc, int RA, int RB, int MODE>
 hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
-    const size_t shm = lds_bytes(a.rows, kHalo1, RB);
+    const size_t shm = lds_bytes(a.rows, kHalo1, RB) +
+                       ((MODE & kP1Cells) != 0 ? 2 * sizeof(unsigned) * a.cell_rows * a.cell_slots : 0);
     // the map-writing and feature variants always run one tile per workgroup
     if constexpr ((MODE & (kP1Maps | kP1Cells)) != 0) {
         if (max_grid) return occupancy(pass1_kernel<Acc, RA, RB, MODE, false>, shm, max_grid);

@@ -167,3 +167,52 @@ def test_autotuner_choice_cache_and_unchanged_output(tmp_path):
         torch.cuda.synchronize()
         for o, r in zip(outs, refs):
             assert torch.equal(o, r)
+
+
+def test_tune_cache_from_environment(tmp_path, monkeypatch):
+    """logfx_tune with no cache path uses the file LOGFX_TUNE_CACHE names:
+    the first context measures and writes it, a second one reads it."""
+    img = scenes.panchromatic(300, 700, 43, n_rect=40, noise_sigma=4.0)
+    _, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    dev = to_device(img)
+    cache = tmp_path / "env_tune.jsonl"
+    monkeypatch.setenv("LOGFX_TUNE_CACHE", str(cache))
+    with logfx.Context(0) as c1:
+        res = c1.tune(dev, params, reps=1)
+    assert res["from_cache"] == 0 and cache.exists() and '"key"' in cache.read_text()
+    with logfx.Context(0) as c2:
+        assert c2.tune(dev, params, reps=1)["from_cache"] == 1
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_alternating_batches_queued_without_sync(ctx, graph):
+    """Three different batches (their own tile counts and image tables) and
+    repeats of them, queued on one stream with no host synchronization in
+    between: each upload goes through the pinned staging set of its turn, an
+    unchanged batch uploads nothing, and every output equals the batch's own
+    output computed alone."""
+    import torch
+    _, lib_t = masks()
+    params = logfx.Params(*lib_t)
+    sets = [_tiles(n=5, seed=61, lo=60, hi=500), _tiles(n=7, seed=62, lo=60, hi=500),
+            _tiles(n=3, seed=63, lo=300, hi=900)]
+    devs = [[to_device(t) for t in s] for s in sets]
+    ctx.set_option(logfx.OPT_GRAPH, graph)
+    try:
+        refs = []
+        for d in devs:
+            refs.append([o.clone() for o in ctx.extract_batch(d, params)])
+        torch.cuda.synchronize()
+        order = [0, 1, 2, 2, 0, 0, 1, 2, 1, 0]
+        outs = [[torch.full(t.shape, 7, dtype=torch.uint8, device="cuda") for t in s] for s in sets]
+        results = []
+        for k in order:
+            ctx.extract_batch(devs[k], params, outs[k])
+            results.append((k, [o.clone() for o in outs[k]]))
+        torch.cuda.synchronize()
+        for k, got in results:
+            for g, r in zip(got, refs[k]):
+                assert torch.equal(g, r), k
+    finally:
+        ctx.set_option(logfx.OPT_GRAPH, 1)
