@@ -548,9 +548,6 @@ ImageDesc image_desc(const logfx_image *img) {
     d.W = img->width;
     d.pitch = img->pitch;
     d.dtype = img->dtype;
-    // 8 pixels per load need the row starts 8-pixel aligned in bytes
-    const size_t esz = img->dtype == LOGFX_U16 ? 2 : 1;
-    d.vec = ((uintptr_t)img->data % (8 * esz) == 0) && (img->pitch % 8 == 0);
     return d;
 }
 

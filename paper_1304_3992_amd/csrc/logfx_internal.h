@@ -54,12 +54,11 @@ struct ImageDesc {
     const void *data;
     long long H, W, pitch;
     int dtype;   // 0 u8, 1 u16
-    int vec;     // rows may be read 8 pixels at a time (data and pitch 8-pixel aligned)
 };
 
 // LDS tile geometry of a pass with halo HL and mask radius rb.  The staged
-// columns start 8-aligned in the image (tiles are 8-multiples wide) so that
-// interior rows are copied 8 pixels per load.
+// columns start at an 8-multiple image column (tiles are 8-multiples wide)
+// so that interior rows are copied in whole 8-pixel chunks.
 __host__ __device__ constexpr int tile_out_width(int halo) { return kTileWaves * (kWave - 2 * halo); }
 __host__ __device__ constexpr int tile_lds_offset(int halo, int rb) { return (8 - (halo + rb) % 8) % 8; }
 __host__ __device__ constexpr int tile_lds_stride(int halo, int rb) {

@@ -233,6 +233,25 @@ __device__ inline uint64_t clamp_bits(uint64_t e, int lo, int hi) {
     return e;
 }
 
+// Eight pixels from element `at` of an image (u16 when `u16`, else u8
+// widened to u16) at any pixel alignment: one 16- or 8-byte global load,
+// which gfx950 serves under the HSA unaligned access mode.
+__device__ inline uint4 load8(const void *data, long long at, bool u16) {
+    typedef __attribute__((address_space(1))) const uint16_t GU16;
+    typedef __attribute__((address_space(1))) const uint8_t GU8;
+    typedef unsigned V4 __attribute__((ext_vector_type(4), aligned(2)));
+    typedef unsigned V2 __attribute__((ext_vector_type(2), aligned(1)));
+    typedef __attribute__((address_space(1))) const V4 GV4;
+    typedef __attribute__((address_space(1))) const V2 GV2;
+    if (u16) {
+        const V4 q = *(GV4 *)((GU16 *)data + at);
+        return make_uint4(q.x, q.y, q.z, q.w);
+    }
+    const V2 q = *(GV2 *)((GU8 *)data + at);
+    return make_uint4(__builtin_amdgcn_perm(0u, q.x, 0x0c010c00u), __builtin_amdgcn_perm(0u, q.x, 0x0c030c02u),
+                      __builtin_amdgcn_perm(0u, q.y, 0x0c010c00u), __builtin_amdgcn_perm(0u, q.y, 0x0c030c02u));
+}
+
 // ------------------------------------------------------------- strips
 // Geometry shared by both passes.  A workgroup owns a tile of kTileWaves strips
 // side by side; each wave's 64 lanes cover image columns base .. base+63,
@@ -270,69 +289,59 @@ struct Strip {
 
     // Stage the input rows y0-HL-RB .. (RH rows) and columns from the
     // 8-aligned origin x0-HL-RB-OFF (stride columns) in LDS as u16, with
-    // clamp-to-edge coordinates.  Tiles whose columns lie inside the image
-    // copy 8 pixels per load, 8 loads in flight per thread.
+    // clamp-to-edge coordinates, in chunks of 8 pixels.  Chunks inside the
+    // image are one load each (load8: any pixel alignment, so neither the
+    // image's start nor its pitch need be aligned), 8 in flight per thread.
+    // In tiles at the left or right border, the chunks that reach past it
+    // (the first nl and the last CPR - nr of each row) are then read pixel
+    // by pixel with clamped columns.  Consecutive threads take consecutive
+    // chunks of a row (coalesced); chunk i of the tile starts at LDS element
+    // 8 i (the LDS row pitch is CPR chunks).
     __device__ void fill(uint16_t *lds, const ImageDesc &img) const {
         constexpr int CPR = stride / 8;
         const int ry0 = y0 - HL - RB, rx0 = x0 - HL - RB - OFF;
         const int nch = RH * CPR;
         const int nt = blockDim.x;
         const long long pitch = img.pitch;
-        if (img.vec && rx0 >= 0 && rx0 + stride <= W) {
-            for (int b = 0; b < nch; b += 8 * nt) {
-                uint4 v[8];
+        const bool u16 = img.dtype == 1;
+        // chunks nl .. nr-1 of a row lie inside the image columns
+        const int nl = rx0 >= 0 ? 0 : min((-rx0 + 7) / 8, CPR);
+        const int nr = max(nl, min(CPR, (W - rx0) / 8));
+        for (int b = 0; b < nch; b += 8 * nt) {
+            uint4 v[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int i = b + k * nt + (int)threadIdx.x;
-                    if (i < nch) {
-                        const int row = i / CPR, ch = i - row * CPR;
-                        const long long at = (long long)min(max(ry0 + row, 0), H - 1) * pitch + rx0 + 8 * ch;
-                        if (img.dtype == 1) {
-                            v[k] = *(const uint4 *)((const uint16_t *)img.data + at);
-                        } else {
-                            const uint2 q = *(const uint2 *)((const uint8_t *)img.data + at);
-                            v[k].x = __builtin_amdgcn_perm(0u, q.x, 0x0c010c00u);
-                            v[k].y = __builtin_amdgcn_perm(0u, q.x, 0x0c030c02u);
-                            v[k].z = __builtin_amdgcn_perm(0u, q.y, 0x0c010c00u);
-                            v[k].w = __builtin_amdgcn_perm(0u, q.y, 0x0c030c02u);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int i = b + k * nt + (int)threadIdx.x;
-                    if (i < nch) {
-                        const int row = i / CPR, ch = i - row * CPR;
-                        *(uint4 *)(lds + row * stride + 8 * ch) = v[k];
-                    }
+            for (int k = 0; k < 8; ++k) {
+                const int i = b + k * nt + (int)threadIdx.x;
+                const int row = i / CPR, ch = i - row * CPR;
+                if (i < nch && ch >= nl && ch < nr) {
+                    const long long at = (long long)min(max(ry0 + row, 0), H - 1) * pitch + rx0 + 8 * ch;
+                    v[k] = load8(img.data, at, u16);
                 }
             }
-        } else {
-            // tiles at the left or right border, and images whose rows are
-            // not 8-pixel aligned: pixel by pixel with clamped coordinates,
-            // consecutive threads on consecutive columns (coalesced), eight
-            // loads in flight per thread before their LDS writes
-            typedef __attribute__((address_space(1))) const uint16_t GU16;
-            typedef __attribute__((address_space(1))) const uint8_t GU8;
-            const int npx = RH * stride;
-            for (int b = 0; b < npx; b += 8 * nt) {
-                uint16_t v[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int i = b + k * nt + (int)threadIdx.x;
-                    if (i < npx) {
-                        const int row = i / stride, col = i - row * stride;
-                        const long long at = (long long)min(max(ry0 + row, 0), H - 1) * pitch +
-                                             min(max(rx0 + col, 0), W - 1);
-                        v[k] = img.dtype == 1 ? ((GU16 *)img.data)[at] : (uint16_t)((GU8 *)img.data)[at];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int i = b + k * nt + (int)threadIdx.x;
-                    if (i < npx) lds[i] = v[k];
-                }
+            for (int k = 0; k < 8; ++k) {
+                const int i = b + k * nt + (int)threadIdx.x;
+                const int row = i / CPR, ch = i - row * CPR;
+                if (i < nch && ch >= nl && ch < nr) *(uint4 *)(lds + 8 * i) = v[k];
             }
+        }
+        const int nb = nl + CPR - nr;   // border chunks per row
+        if (nb == 0) return;
+        typedef __attribute__((address_space(1))) const uint16_t GU16;
+        typedef __attribute__((address_space(1))) const uint8_t GU8;
+        for (int e = (int)threadIdx.x; e < RH * nb; e += nt) {
+            const int row = e / nb, j = e - row * nb;
+            const int ch = j < nl ? j : nr + (j - nl);
+            const long long at = (long long)min(max(ry0 + row, 0), H - 1) * pitch;
+            const int c0 = rx0 + 8 * ch;
+            unsigned p[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const long long o = at + min(max(c0 + q, 0), W - 1);
+                p[q] = u16 ? (unsigned)((GU16 *)img.data)[o] : (unsigned)((GU8 *)img.data)[o];
+            }
+            *(uint4 *)(lds + 8 * (row * CPR + ch)) =
+                make_uint4(p[0] | p[1] << 16, p[2] | p[3] << 16, p[4] | p[5] << 16, p[6] | p[7] << 16);
         }
     }
 };

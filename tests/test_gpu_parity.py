@@ -132,6 +132,32 @@ def test_pitch_larger_than_width(ctx):
     compare(F, o, smooth=True)
 
 
+@pytest.mark.parametrize("dtype,bits,off,pitch", [(np.uint8, 0, 3, 1001), (np.uint16, 11, 5, 517),
+                                                  (np.uint8, 0, 1, 777), (np.uint16, 11, 1, 1203)])
+def test_unaligned_base_and_pitch(ctx, dtype, bits, off, pitch):
+    """Images whose first pixel and row pitch are at odd element offsets in
+    their buffer (interior chunks are read by unaligned vector loads): the
+    map equals the same image's map from a contiguous aligned buffer bit for
+    bit, and the oracle's under the band rule.  Widths span several tiles
+    and a ragged tail."""
+    import torch
+    img = _scene_crop(230, pitch - 13, 25 + off, 11 if bits else 8).astype(dtype)
+    H, W = img.shape
+    orc_t, lib_t = masks()
+    a = img.view(np.int16) if dtype == np.uint16 else img
+    buf = torch.zeros(off + H * pitch, dtype=torch.from_numpy(a[:1, :1].copy()).dtype)
+    flat = torch.from_numpy(np.ascontiguousarray(a))
+    for y in range(H):
+        buf[off + y * pitch: off + y * pitch + W] = flat[y]
+    dev = buf.cuda().as_strided((H, W), (pitch, 1), off)
+    params = logfx.Params(*lib_t)
+    F = ctx.extract(dev, params, bits=bits)
+    ref = ctx.extract(to_device(img), params, bits=bits)
+    torch.cuda.synchronize()
+    assert torch.equal(F, ref)
+    compare(F.cpu().numpy(), run_oracle(img, orc_t), smooth=True)
+
+
 def test_repeatable_and_tile_independent(ctx):
     """Two runs give identical bytes, and so does a context with another tile
     shape (tiles change the reduction order of the global sums only)."""
