@@ -262,11 +262,15 @@ enum {
     LOGFX_OPT_ROWS2 = 2,      /* the same for pass 2 (default 64) */
     LOGFX_OPT_PERSISTENT = 3, /* batches: 1 = persistent launch, 0 = one workgroup per tile (default) */
     LOGFX_OPT_GRAPH = 4,      /* batches: 1 = replay a captured hipGraph (default), 0 = direct launches */
-    LOGFX_OPT_STORE_Z = 5     /* 1 (default) = pass 1 stores the crossing strengths of every pixel in
+    LOGFX_OPT_STORE_Z = 5,    /* 1 (default) = pass 1 stores the crossing strengths of every pixel in
                                  context memory (8 bytes per pixel on the integer path, 16 on FP64) and
                                  pass 2 reads them; 0 = pass 2 recomputes them from the image (no such
                                  memory).  Both give the same output; a call whose strength memory
                                  cannot be allocated recomputes. */
+    LOGFX_OPT_PACKED_LOG = 6  /* 1 (default) = on the integer path, pass 1 evaluates the LoG on packed
+                                 16-bit sums of pixel pairs (two taps per multiply-add) where the
+                                 pixels have at most 13 bits and every tap but the centre fits 16
+                                 bits; 0 = always the 32-bit form.  Both give the same bits. */
 };
 int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value);
 int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value);

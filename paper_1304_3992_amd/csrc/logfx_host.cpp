@@ -17,6 +17,7 @@
 #include <iterator>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "logfx_gate.h"
@@ -55,6 +56,7 @@ struct logfx_ctx {
     bool persistent = false;         // batches: one resident grid walks all tiles
     bool graph = true;               // batches: replay a captured hipGraph
     bool store_z = true;             // pass 1 stores the strengths, pass 2 reads them
+    bool pack_log = true;            // integer LoG on packed 16-bit sums where it applies
     void *zmap = nullptr;            // strength pairs of the images of a call
     long long zcap = 0;              // bytes
     uint8_t *cmap = nullptr;         // 0/1 maps between the levels of a median cascade
@@ -399,12 +401,34 @@ struct Plan {
     double maxpix = 255.0;
     bool std5 = false;    // the 5x5 first deviation stage is on (std5_max >= 0)
     bool inexact = false; // the FP64 LoG sums round (LOGFX_ALLOW_INEXACT)
+    bool pk_ok = false;   // the integer LoG may run on packed 16-bit sums (kP1Packed)
     int ncas = 0;         // further median levels (applied where the first level is)
     int cas[3] = {0, 0, 0};
     int region = 0;       // > 0: the gate decides per region x region square (single images)
     int gx = 1, gy = 1;   // regions per row / per column (powers of two)
     int lgx = 0, lgy = 0; // their log2
 };
+
+// The taps of the packed integer LoG (layout in logfx_internal.h): entry
+// v(d, c) takes the tap of its orbit, which is the mask's tap at row offset
+// d and column offset c (the masks are D4-symmetric).  False when one of
+// them, the centre's aside, does not fit int16.
+bool fill_packed_taps(const Plan &pl, OrbitTapsI &t) {
+    for (int slot = 0; slot < 2; ++slot) {
+        const MaskInfo &mi = pl.mi[pl.order[slot]];
+        const int r = mi.radius, s = mi.size;
+        auto tap = [&](int d, int c) -> double { return d > r || c > r ? 0.0 : mi.k[(r + d) * s + (r + c)]; };
+        for (int d = 0; d <= kMaxRadius; ++d)
+            for (int m = 0; m < kPkPerRow; ++m) {
+                const double lo = m == 0 ? (d == 0 ? 0.0 : tap(d, 0)) : tap(d, 2 * m - 1);
+                const double hi = m == 0 ? 0.0 : tap(d, 2 * m);
+                if (!(lo >= -32768.0 && lo <= 32767.0 && hi >= -32768.0 && hi <= 32767.0)) return false;
+                t.pk[slot][d * kPkPerRow + m] =
+                    (unsigned)(uint16_t)(int16_t)lo | (unsigned)(uint16_t)(int16_t)hi << 16;
+            }
+    }
+    return true;
+}
 
 int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Plan &pl) {
     if (!img || !p) return set_err(ctx, LOGFX_EINVAL, "image or params is NULL");
@@ -463,6 +487,9 @@ int check_all(logfx_ctx *ctx, const logfx_image *img, const logfx_params *p, Pla
     else pl.order[0] = 1, pl.order[1] = 0;
     pl.ra = std::max(1, std::min(r0, r1));
     pl.rb = std::max(1, std::max(r0, r1));
+    // packed 16-bit sums: every v(d, c) (at most four pixels) below 2^15
+    OrbitTapsI probe;
+    pl.pk_ok = pl.path == LOGFX_PATH_INT32 && pl.maxpix <= 8191.0 && fill_packed_taps(pl, probe);
     pl.std5 = p->std5_max >= 0.0;
     if (p->gate_region < 0) return set_err(ctx, LOGFX_EINVAL, "gate_region %d < 0", p->gate_region);
     pl.region = 0;
@@ -509,6 +536,10 @@ void fill_taps(const Plan &pl, Taps &t) {
             for (int j = 0; j <= i; ++j) t.k[slot][orbit_index(i, j)] = (V)mi.k[(r + i) * s + (r + j)];
     }
 }
+
+// The packed integer form runs when the plan allows it and the context
+// does not turn it off (LOGFX_OPT_PACKED_LOG).
+bool use_packed(const logfx_ctx *ctx, const Plan &pl) { return pl.pk_ok && ctx->pack_log; }
 
 // ------------------------------------------------------------ one call
 // Tiling of one image in both passes.
@@ -760,6 +791,7 @@ struct Launches {
     FinalizeArgs fin;
     int grid1, grid2;
     int path, ra, rb;
+    bool packed;                   // pass 1 on packed 16-bit sums (integer path)
     bool dbg;
     bool storez;
     // median cascade: further levels after pass 2 (pass 2 writes the
@@ -786,12 +818,14 @@ enum Until { UNTIL_PASS1 = 0, UNTIL_FEATURES = 1, UNTIL_DECISION = 2, UNTIL_OUTP
 
 template <class Taps, class V>
 void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *const L[2],
-               double *const Z[2], Pass1Args<Taps> &a1, Pass2Args<Taps> &a2, bool &dbg) {
+               double *const Z[2], Pass1Args<Taps> &a1, Pass2Args<Taps> &a2, bool &dbg, bool packed) {
     std::memset(&a1, 0, sizeof a1);
     std::memset(&a2, 0, sizeof a2);
     a1.L = a2.L = c.L;
     fill_taps<Taps, V>(c.pl, a1.taps);
     fill_taps<Taps, V>(c.pl, a2.taps);
+    if constexpr (std::is_same<Taps, OrbitTapsI>::value)
+        if (packed) fill_packed_taps(c.pl, a1.taps);
     dbg = false;
     for (int slot = 0; slot < 2; ++slot) {
         const int u = c.pl.order[slot];
@@ -826,7 +860,8 @@ void fill_args(const Call &c, logfx_ctx *ctx, const logfx_params *p, double *con
 hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int until) {
     hipError_t e;
     const bool i32 = k.path == LOGFX_PATH_INT32;
-    const int mode = (k.dbg ? kP1Maps : 0) | (k.features ? kP1Cells : 0) | (k.storez ? kP1StoreZ : 0);
+    const int mode = (k.dbg ? kP1Maps : 0) | (k.features ? kP1Cells : 0) | (k.storez ? kP1StoreZ : 0) |
+                     (k.packed ? kP1Packed : 0);
     if (k.features && (e = gate::launch_zero_cells(k.cells, k.nsets, s)) != hipSuccess) return e;
     e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, mode, k.grid1, s)
             : launch_pass1_d(k.ra, k.rb, k.p1.d, mode, k.grid1, s);
@@ -877,8 +912,9 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
     k.ra = c.pl.ra;
     k.rb = c.pl.rb;
     k.storez = c.storez;
-    if (k.path == LOGFX_PATH_INT32) fill_args<OrbitTapsI, int>(c, ctx, p, L, Z, k.p1.i, k.p2.i, k.dbg);
-    else fill_args<OrbitTapsD, double>(c, ctx, p, L, Z, k.p1.d, k.p2.d, k.dbg);
+    k.packed = use_packed(ctx, c.pl);
+    if (k.path == LOGFX_PATH_INT32) fill_args<OrbitTapsI, int>(c, ctx, p, L, Z, k.p1.i, k.p2.i, k.dbg, k.packed);
+    else fill_args<OrbitTapsD, double>(c, ctx, p, L, Z, k.p1.d, k.p2.d, k.dbg, false);
     k.gx = c.pl.gx;
     k.gy = c.pl.gy;
     k.nsets = c.n * c.pl.gx * c.pl.gy;
@@ -941,7 +977,7 @@ int build_launches(logfx_ctx *ctx, const Call &c, const logfx_params *p, double 
         // a persistent launch: as many workgroups as fit on the device
         int m1 = 0, m2 = 0;
         const bool i32 = k.path == LOGFX_PATH_INT32;
-        const int mode = k.storez ? kP1StoreZ : 0;
+        const int mode = (k.storez ? kP1StoreZ : 0) | (k.packed ? kP1Packed : 0);
         hipError_t e = i32 ? launch_pass1_i(k.ra, k.rb, k.p1.i, mode, 0, nullptr, &m1)
                            : launch_pass1_d(k.ra, k.rb, k.p1.d, mode, 0, nullptr, &m1);
         if (e == hipSuccess && k.storez)
@@ -1070,7 +1106,8 @@ int run(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *p, u
     if (log_on())
         log_line("%s: %d image(s), first %lld x %lld, %s path, radii %d/%d, tiles %d/%d (rows %d/%d), %s, smooth %d%s%s",
              maps ? "extract_maps" : (n > 1 ? "extract_batch" : "extract"), n, (long long)imgs[0].height,
-             (long long)imgs[0].width, c.pl.path == LOGFX_PATH_INT32 ? "int32" : "fp64", c.pl.ra, c.pl.rb,
+             (long long)imgs[0].width,
+             c.pl.path != LOGFX_PATH_INT32 ? "fp64" : k.packed ? "int32 (packed)" : "int32", c.pl.ra, c.pl.rb,
              c.L.total1, c.L.total2, c.rows1, ctx->tiles.rows2, c.storez ? "stored strengths" : "recomputed strengths",
              p->smooth, gated ? " (gated)" : "", use_graph ? ", graph" : "");
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1147,7 +1184,8 @@ std::string tune_key(logfx_ctx *ctx, const Call &c, const logfx_params *p, const
         if (colon != std::string::npos) arch.resize(colon);
     }
     std::ostringstream k;
-    k << arch << "|" << (c.pl.path == LOGFX_PATH_INT32 ? "int32" : "fp64") << "|r" << c.pl.ra << c.pl.rb
+    k << arch << "|" << (c.pl.path != LOGFX_PATH_INT32 ? "fp64" : use_packed(ctx, c.pl) ? "int32pk" : "int32")
+      << "|r" << c.pl.ra << c.pl.rb
       << "|" << (img0->dtype == LOGFX_U8 ? "u8" : "u16") << "|med"
       << (p->smooth != LOGFX_SMOOTH_NEVER ? p->median_size : 0) << (p->smooth == LOGFX_SMOOTH_GATE ? "g" : "")
       << "|" << (c.n > 1 ? "batch" : "single") << (c.pl.std5 ? "|s5" : "");
@@ -1446,6 +1484,7 @@ int logfx_set_option(logfx_ctx *ctx, int32_t option, int64_t value) {
     case LOGFX_OPT_PERSISTENT: ctx->persistent = value != 0; return LOGFX_OK;
     case LOGFX_OPT_GRAPH: ctx->graph = value != 0; return LOGFX_OK;
     case LOGFX_OPT_STORE_Z: ctx->store_z = value != 0; return LOGFX_OK;
+    case LOGFX_OPT_PACKED_LOG: ctx->pack_log = value != 0; return LOGFX_OK;
     default: return set_err(ctx, LOGFX_EINVAL, "unknown option %d", option);
     }
 }
@@ -1458,6 +1497,7 @@ int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value) {
     case LOGFX_OPT_PERSISTENT: *value = ctx->persistent; return LOGFX_OK;
     case LOGFX_OPT_GRAPH: *value = ctx->graph; return LOGFX_OK;
     case LOGFX_OPT_STORE_Z: *value = ctx->store_z; return LOGFX_OK;
+    case LOGFX_OPT_PACKED_LOG: *value = ctx->pack_log; return LOGFX_OK;
     default: return set_err(ctx, LOGFX_EINVAL, "unknown option %d", option);
     }
 }

@@ -26,6 +26,7 @@ constexpr int kHalo2Z5 = 4;
 constexpr int kP1Maps = 1;     // FP64 maps of L and Z (single images, for inspection)
 constexpr int kP1Cells = 2;    // the gate's per-cell sums
 constexpr int kP1StoreZ = 4;   // the (Z_1, Z_2) pair of every pixel for pass 2
+constexpr int kP1Packed = 8;   // integer path: the LoG on packed 16-bit pixel sums
 
 // Side of the cell grid over which pass 1 sums the smoothing gate's
 // features (kGateCells x kGateCells cells per image).
@@ -35,9 +36,29 @@ constexpr int kGateCells = 1 << kGateCellsLog2;
 // Orbit index of the D4 orbit {(+-i, +-j), (+-j, +-i)}, 0 <= j <= i.
 __host__ __device__ constexpr int orbit_index(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// Packed form of the integer LoG (kP1Packed).  With v(d, c) the sum of
+// the pixels at row offsets +-d and column offsets +-c (v(0, 0) the centre,
+// v(d, 0) two pixels, v(0, c) two, v(d, c) four), each entry lies in exactly
+// one D4 orbit, that of (max(d, c), min(d, c)), so
+//   L = sum over d, c in 0..R of k'(d, c) v(d, c),  k'(d, c) = k_orbit.
+// Per row offset d the entries are packed in 16-bit halves, kPkPerRow
+// words: (v(d, 0), unused), (v(d, 1), v(d, 2)), (v(d, 3), v(d, 4)); the
+// taps k' are packed the same way (0 in unused halves and past the mask's
+// radius), word d * kPkPerRow + m, and multiplied two at a time
+// (v_dot2_i32_i16).  The centre v(0, 0) (one pixel) takes the orbit tap k[0]
+// of the 32-bit form in a 24-bit multiply, since that tap alone may exceed
+// 16 bits; word 0 is unused.  Valid when every v fits int16 (pixels below
+// 2^13) and every other tap does too; the host checks both.
+constexpr int kPkPerRow = 3;
+constexpr int kPkTaps = (kMaxRadius + 1) * kPkPerRow;
+
 // Orbit taps of both masks, in integer grid units.  The integer path keeps
-// them as int (they fit 24-bit signed); the FP64 path as double.
-struct OrbitTapsI { int k[2][kMaxOrbits]; };
+// them as int (they fit 24-bit signed), and in the packed form above when
+// it applies; the FP64 path as double.
+struct OrbitTapsI {
+    int k[2][kMaxOrbits];
+    unsigned pk[2][kPkTaps];
+};
 struct OrbitTapsD { double k[2][kMaxOrbits]; };
 
 // Device-side statistics written by the finalize kernel (LoG grid units).

@@ -121,11 +121,73 @@ __device__ inline void log_pair(const int (&h)[2 * RB + 1][RB + 1],
     out[1] = l1;
 }
 
-// Opposite strict signs of p and q.
-__device__ inline bool opposite(int p, int q) {
-    // signs in {-1, 0, 1}; only -1 ^ 1 and 1 ^ -1 give -2
-    return (min(max(p, -1), 1) ^ min(max(q, -1), 1)) == -2;
+// Packed integer form (kP1Packed): pairs of 16-bit sums in one VGPR, the
+// layout the taps' pk words describe.
+typedef short pk2 __attribute__((ext_vector_type(2)));
+__device__ inline pk2 as_pk2(unsigned v) { return __builtin_bit_cast(pk2, v); }
+__device__ inline unsigned as_u32(pk2 v) { return __builtin_bit_cast(unsigned, v); }
+__host__ __device__ constexpr int pk_words(int r) { return 1 + (r + 1) / 2; }
+
+// (x.lo + y.hi, x.hi + y.lo): one v_pk_add_u16 with the halves of y swapped
+// by its operand selection
+__device__ inline pk2 add_swapped(unsigned x, unsigned y) {
+    unsigned r;
+    asm("v_pk_add_u16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0]" : "=v"(r) : "v"(x), "v"(y));
+    return as_pk2(r);
 }
+
+// k * (low 16 bits of w), the 16 bits taken by the operand selection
+__device__ inline int mul_lo16(int k, pk2 w) {
+    int r;
+    asm("v_mul_i32_i24_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(r) : "s"(k), "v"(as_u32(w)));
+    return r;
+}
+
+// One row of pair sums at the lane's column, packed: g[0] = (I(x), I(x + 1))
+// (the high half has zero taps), g[1] = (h_1, h_2), g[2] = (h_3, h_4),
+// h_c = I(x - c) + I(x + c).  One unaligned 16-byte LDS read gives
+// I(x - 4) .. I(x + 3) and one 2-byte read I(x + 4); the pairs (I1, I2)
+// and (I3, I4) come from funnel shifts.  (Two 16-byte reads, at x - 4 and
+// x - 3, spare the shifts but measured 35 % slower: the LDS, not the VALU,
+// then bounds the kernel.)  For every mask radius these columns lie inside
+// the staged row (its leading alignment columns and trailing padding hold
+// them).
+template <int RB>
+__device__ inline void load_hrow_pk(const uint16_t *p, pk2 (&g)[pk_words(RB)]) {
+    typedef unsigned V4 __attribute__((ext_vector_type(4), aligned(2)));
+    const V4 a = *(const V4 *)(p - 4);   // (I-4, I-3) (I-2, I-1) (I0, I1) (I2, I3)
+    g[0] = as_pk2(a.z);
+    g[1] = add_swapped(__builtin_amdgcn_alignbit(a.w, a.z, 16), a.y);   // (I1, I2) + (I-1, I-2)
+    if constexpr (pk_words(RB) > 2) {
+        const unsigned i4 = p[4];
+        g[2] = add_swapped(__builtin_amdgcn_alignbit(i4, a.w, 16), a.x);   // (I3, I4) + (I-3, I-4)
+    }
+}
+
+// Both LoG responses of the centre row of the packed ring (ring row RB):
+// the centre pixel times its 32-bit tap, then v(d, .) of the row pair at
+// +-d by packed adds and two taps per v_dot2_i32_i16.
+template <int RA, int RB>
+__device__ inline void log_pair_pk(const pk2 (&g)[2 * RB + 1][pk_words(RB)], const OrbitTapsI &t, int (&out)[2]) {
+    int l0 = mul_lo16(t.k[0][0], g[RB][0]);
+    int l1 = mul_lo16(t.k[1][0], g[RB][0]);
+#pragma unroll
+    for (int d = 0; d <= RB; ++d) {
+#pragma unroll
+        for (int m = d == 0 ? 1 : 0; m < pk_words(RB); ++m) {
+            const pk2 v = d == 0 ? g[RB][m] : g[RB - d][m] + g[RB + d][m];
+            l1 = __builtin_amdgcn_sdot2(v, as_pk2(t.pk[1][d * kPkPerRow + m]), l1, false);
+            if (d <= RA && m < pk_words(RA))
+                l0 = __builtin_amdgcn_sdot2(v, as_pk2(t.pk[0][d * kPkPerRow + m]), l0, false);
+        }
+    }
+    out[0] = l0;
+    out[1] = l1;
+}
+
+// Opposite strict signs of p and q.
+__device__ inline bool opposite(int p, int q) { return (min(p, q) < 0) & (max(p, q) > 0); }
 __device__ inline bool opposite(double p, double q) { return p * q < 0.0; }
 
 // Zero-crossing strength (Sec. 3.2) of centre a with neighbours up, dn, lf,
@@ -428,9 +490,13 @@ template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4
 #ifndef LOGFX_P1_CELL_WAVES
 #define LOGFX_P1_CELL_WAVES 3
 #endif
+#ifndef LOGFX_P1_PK_WAVES
+#define LOGFX_P1_PK_WAVES 4
+#endif
 template <class Acc, int MODE, bool LOOP>
 constexpr int kPass1Waves =
     !std::is_same<Acc, int>::value ? kMinWaves<Acc>
+    : (MODE & kP1Packed) != 0 ? ((MODE & kP1Cells) != 0 || LOOP ? 4 : LOGFX_P1_PK_WAVES)
     : (MODE & kP1Cells) != 0       ? LOGFX_P1_CELL_WAVES
     : ((MODE & kP1StoreZ) != 0 && LOOP) ? 3
                                         : kMinWaves<Acc>;
@@ -466,9 +532,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     }
     __syncthreads();
 
-    int h[P][RB + 1];
+    // ring of pair-sum rows: 32-bit, or packed (kP1Packed)
+    constexpr bool PK = (MODE & kP1Packed) != 0;
+    static_assert(!PK || std::is_same<Acc, int>::value, "the packed form is integer only");
+    int h[PK ? 1 : P][RB + 1];
+    pk2 hp[PK ? P : 1][pk_words(RB)];
 #pragma unroll
-    for (int s = 0; s < P - 1; ++s) load_hrow<RB>(lds + s * g.stride + g.lc, h[s + 1]);
+    for (int s = 0; s < P - 1; ++s) {
+        if constexpr (PK) load_hrow_pk<RB>(lds + s * g.stride + g.lc, hp[s + 1]);
+        else load_hrow<RB>(lds + s * g.stride + g.lc, h[s + 1]);
+    }
     Acc L[2][3] = {{0, 0, 0}, {0, 0, 0}};   // rows t-2, t-1, t per mask
     double sz[2] = {0.0, 0.0}, sq[2] = {0.0, 0.0};
     int cnt[2] = {0, 0};
@@ -525,15 +598,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     // rolled.
     auto step = [&](const int si, auto clamp) __attribute__((always_inline)) {
         constexpr bool C = decltype(clamp)::value;
+        Acc Ln[2];
+        if constexpr (PK) {
 #pragma unroll
-        for (int s = 0; s < P - 1; ++s)
+            for (int s = 0; s < P - 1; ++s)
 #pragma unroll
-            for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
-        load_hrow<RB>(lrow, h[P - 1]);
+                for (int m = 0; m < pk_words(RB); ++m) hp[s][m] = hp[s + 1][m];
+            load_hrow_pk<RB>(lrow, hp[P - 1]);
+            log_pair_pk<RA, RB>(hp, a.taps, Ln);
+        } else {
+#pragma unroll
+            for (int s = 0; s < P - 1; ++s)
+#pragma unroll
+                for (int j = 0; j <= RB; ++j) h[s][j] = h[s + 1][j];
+            load_hrow<RB>(lrow, h[P - 1]);
+            log_pair<Acc, RA, RB>(h, a.taps, Ln);
+        }
         lrow += g.stride;
         const int t = t0 + si;
-        Acc Ln[2];
-        log_pair<Acc, RA, RB>(h, a.taps, Ln);
         ring_push<C>(L[0], Ln[0], t, g.H);
         ring_push<C>(L[1], Ln[1], t, g.H);
         // zero crossings of row t - 1 (valid from the third step on)
@@ -568,7 +650,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         if constexpr ((MODE & kP1Cells) != 0) {
             // every lane accumulates; the halo rows before the strip are
             // dropped below and the non-output lanes at the flush
-            fv += (unsigned)h[RB - 1][0];   // pixel (r, xc)
+            // pixel (r, xc): the centre of ring row RB - 1
+            if constexpr (PK) fv += as_u32(hp[RB - 1][0]) & 0xFFFFu;
+            else fv += (unsigned)h[RB - 1][0];
             fc += nonzero(zr[0]) + (nonzero(zr[1]) << 16);
             if (si < 2) fv = fc = 0;
             else if (r + 1 == fnext || r == g.y0 + g.Rv - 1) flush(r);

@@ -17,7 +17,8 @@ namespace logfx {
 namespace {   // one copy per radius pair: internal linkage keeps the units' copies apart
 
 // Pass-1 variants built: statistics only, maps, cells, stored strengths,
-// stored strengths with cells.
+// stored strengths with cells; on the integer path each also in the packed
+// form.
 template <class Acc>
 hipError_t pass1_any(const Pass1Args<typename kern::AccOps<Acc>::Taps> &a, int mode, int grid, hipStream_t s,
                      int *max_grid) {
@@ -27,8 +28,19 @@ hipError_t pass1_any(const Pass1Args<typename kern::AccOps<Acc>::Taps> &a, int m
     case kP1Cells: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1Cells>(a, grid, s, max_grid);
     case kP1StoreZ: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1StoreZ>(a, grid, s, max_grid);
     case kP1StoreZ | kP1Cells: return kern::p1<Acc, LOGFX_RA, LOGFX_RB, kP1StoreZ | kP1Cells>(a, grid, s, max_grid);
-    default: return hipErrorInvalidValue;
     }
+    if constexpr (std::is_same<Acc, int>::value) {   // the same on packed 16-bit sums
+        constexpr int K = kP1Packed;
+        switch (mode) {
+        case K: return kern::p1<int, LOGFX_RA, LOGFX_RB, K>(a, grid, s, max_grid);
+        case K | kP1Maps: return kern::p1<int, LOGFX_RA, LOGFX_RB, K | kP1Maps>(a, grid, s, max_grid);
+        case K | kP1Cells: return kern::p1<int, LOGFX_RA, LOGFX_RB, K | kP1Cells>(a, grid, s, max_grid);
+        case K | kP1StoreZ: return kern::p1<int, LOGFX_RA, LOGFX_RB, K | kP1StoreZ>(a, grid, s, max_grid);
+        case K | kP1StoreZ | kP1Cells:
+            return kern::p1<int, LOGFX_RA, LOGFX_RB, K | kP1StoreZ | kP1Cells>(a, grid, s, max_grid);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 }  // namespace
 

@@ -30,7 +30,7 @@ EXPORTS = ["logfx_version", "logfx_create", "logfx_destroy", "logfx_last_error",
            "logfx_gate_step", "logfx_gate", "logfx_gate_save_state", "logfx_gate_load_state",
            "logfx_extract_noalloc"]
 GATE_NPARAM, GATE_CELLS, GATE_MAX_BATCH = 14369, 128, 4096
-OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH, OPT_STORE_Z = 1, 2, 3, 4, 5
+OPT_ROWS1, OPT_ROWS2, OPT_PERSISTENT, OPT_GRAPH, OPT_STORE_Z, OPT_PACKED_LOG = 1, 2, 3, 4, 5, 6
 ALLOW_INEXACT = 1
 
 

@@ -166,6 +166,7 @@ def test_gate_constants_and_smooth_modes(lib):
         assert re.search(rf"#define {name} {val}\b", text), name
     assert re.search(r"LOGFX_SMOOTH_GATE = 2", text)
     assert re.search(r"LOGFX_OPT_STORE_Z = 5", text) and logfx.OPT_STORE_Z == 5
+    assert re.search(r"LOGFX_OPT_PACKED_LOG = 6", text) and logfx.OPT_PACKED_LOG == 6
     from oracle import gate as og
     assert og.NPARAM == logfx.GATE_NPARAM
     p = _params()

@@ -70,6 +70,92 @@ def test_maps_bit_exact(ctx, name, make, bits, pair, gb):
         assert np.array_equal(g, ref), (k, int((g != ref).sum()))
 
 
+PACKED_CASES = [
+    # (name, image factory, bits, mask pair, grid bits, packed form applies)
+    ("u8_r2r4", lambda: _rand((131, 301), 255, 40, np.uint8), 0, ((5, 0.8), (9, 1.4)), 16, True),
+    ("u11_r2r4", lambda: _scene_crop(200, 333, 41, 11), 11, ((5, 0.8), (9, 1.4)), 16, True),
+    ("u13_r1r2", lambda: _rand((90, 260), 8191, 42, np.uint16), 13, ((3, 0.5), (5, 0.8)), 14, True),
+    # 13-bit extremes: sums of four pixels reach 4 * 8191, the top of int16
+    ("u13_extremes", lambda: ((np.indices((96, 200)).sum(0) // 3 % 2) * 8191 +
+                              (_rand((96, 200), 1, 48, np.uint16) * 8191)).clip(0, 8191).astype(np.uint16),
+     13, ((5, 0.8), (9, 1.4)), 13, True),
+    ("u12_r3r3", lambda: _rand((75, 140), 4095, 43, np.uint16), 12, ((7, 1.0), (7, 1.2)), 15, True),
+    ("u12_r4r4_wide", lambda: _rand((60, 500), 4095, 44, np.uint16), 12, ((9, 1.4), (9, 2.0)), 12, True),
+    ("u8_r1r1", lambda: _rand((65, 129), 255, 45, np.uint8), 0, ((3, 0.5), (3, 0.9)), 16, True),
+    # 14-bit pixels on a 12-bit tap grid: exact in int32, but four pixels
+    # overflow int16, so the 32-bit form runs whatever the option says
+    ("u14_grid12_r2r4", lambda: _rand((70, 300), 16383, 46, np.uint16), 14, ((5, 0.8), (9, 1.4)), 12, False),
+]
+
+
+@pytest.mark.parametrize("name,make,bits,pair,gb,packed", PACKED_CASES, ids=[c[0] for c in PACKED_CASES])
+def test_packed_and_32bit_forms_agree(ctx, name, make, bits, pair, gb, packed):
+    """The integer path with the LoG on packed 16-bit sums (the default where
+    pixels and taps fit) and in the 32-bit form: L and Z bit-identical to each
+    other and to the oracle, and the same output map."""
+    import torch
+    img = make()
+    orc_t, lib_t = masks(pair, gb)
+    params = logfx.Params(*lib_t)
+    dev = to_device(img)
+    assert logfx.check_params(logfx.image(dev, bits), params) == logfx.PATH_INT32
+    o = run_oracle(img, orc_t)
+    got = {}
+    try:
+        for form in (1, 0):
+            ctx.set_option(logfx.OPT_PACKED_LOG, form)
+            maps = ctx.extract_maps(dev, params, bits=bits)
+            out = ctx.extract(dev, params, bits=bits)
+            torch.cuda.synchronize()
+            got[form] = ({k: maps[k].cpu().numpy() for k in ("L1", "L2", "Z1", "Z2")}, out.cpu().numpy())
+    finally:
+        ctx.set_option(logfx.OPT_PACKED_LOG, 1)
+    for k in ("L1", "L2", "Z1", "Z2"):
+        assert np.array_equal(got[1][0][k], o[k]), (k, int((got[1][0][k] != o[k]).sum()))
+        assert np.array_equal(got[0][0][k], got[1][0][k]), k
+    assert np.array_equal(got[0][1], got[1][1])
+    compare(got[1][1], o, smooth=True)
+
+
+SELECTION_SCRIPT = r"""
+import sys
+sys.path.insert(0, %r)
+sys.path.insert(0, %r)
+import numpy as np, torch
+from paper_1304_3992_amd import logfx
+from parity import masks, to_device
+ctx = logfx.Context(0)
+rng = np.random.default_rng(47)
+cases = [(rng.integers(0, 2048, (40, 70)).astype(np.uint16), 11, 16, 1),
+         (rng.integers(0, 2048, (41, 70)).astype(np.uint16), 11, 16, 0),
+         (rng.integers(0, 16384, (42, 70)).astype(np.uint16), 14, 12, 1)]
+for img, bits, gb, form in cases:
+    ctx.set_option(logfx.OPT_PACKED_LOG, form)
+    ctx.extract(to_device(img), logfx.Params(*masks(grid_bits=gb)[1]), bits=bits)
+    torch.cuda.synchronize()
+print("done")
+"""
+
+
+def test_packed_form_selection_logged():
+    """Which form runs, as the call log states it (a child process: the
+    log setting is read once): packed for 11-bit pixels, the 32-bit form
+    when the option turns it off, and for 14-bit pixels whatever the
+    option says."""
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ, LOGFX_LOG="1")
+    r = subprocess.run([sys.executable, "-c", SELECTION_SCRIPT % (os.path.dirname(here), here)], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "done" in r.stdout, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[liblogfx] extract:")]
+    assert len(lines) == 3, r.stderr[-2000:]
+    assert "40 x 70, int32 (packed) path" in lines[0]
+    assert "41 x 70, int32 path" in lines[1]
+    assert "42 x 70, int32 path" in lines[2]
+
+
 EXTRACT_CASES = [
     ("c1", lambda: scenes.config1(), 0, {}),
     ("c1_nosmooth", lambda: scenes.config1(), 0, dict(smooth=False)),
