@@ -277,10 +277,11 @@ int logfx_get_option(logfx_ctx *ctx, int32_t option, int64_t *value);
 
 /* Autotuner (the launch-parameter sweep of Table 4, Sec. 6.2.3, made
  * automatic).  Runs the given call (one image, or a batch when n > 1) with
- * each candidate strip height for pass 1 and pass 2 (32, 48, 64, 96 rows,
- * as far as they fit in LDS) and, for batches, with and without the
- * persistent launch, `reps` timed repetitions each, and keeps the fastest
- * in the context (LOGFX_OPT_ROWS1/ROWS2/PERSISTENT).  The outputs are
+ * each candidate strip height for pass 1 and pass 2 (32, 40, 48, 56, 64, 96
+ * rows, as far as they fit in LDS) and, for batches, with and without the
+ * persistent launch, `reps` timed repetitions each, in two round-robin
+ * rounds (each candidate keeps its faster round), and keeps the fastest in
+ * the context (LOGFX_OPT_ROWS1/ROWS2/PERSISTENT).  The outputs are
  * written as by the call itself.  cache_path (nullable): a text file of
  * JSON lines keyed by device architecture, arithmetic path, mask radii,
  * pixel type, smoothing and batch/single; an entry found there is applied

@@ -1753,7 +1753,12 @@ int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_p
         const TileCfg saved = ctx->tiles;
         const bool saved_p = ctx->persistent, saved_g = ctx->graph, saved_t = ctx->timing;
         ctx->graph = false;   // direct launches, so that each kernel is timed on its own
-        const int cand[] = {32, 48, 64, 96};
+        const int cand[] = {32, 40, 48, 56, 64, 96};
+        constexpr int ncand = sizeof cand / sizeof cand[0];
+        // the candidates are timed round-robin, twice, and each keeps its
+        // faster round: one pass over them in order favours whichever runs
+        // first (the clock drops as the device warms up)
+        constexpr int kRounds = 2;
         // time one configuration: the sums of pass-1, pass-2 and whole-call milliseconds
         auto measure = [&](double ms[4]) -> int {
             int r;
@@ -1765,29 +1770,41 @@ int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_p
             int64_t calls;
             return logfx_timing_read(ctx, ms, &calls);
         };
-        double best1 = 1e300, best2 = 1e300;
+        double t1[ncand], t2[ncand];
+        for (int i = 0; i < ncand; ++i) t1[i] = t2[i] = 1e300;
+        for (int round = 0; round < kRounds && rc == LOGFX_OK; ++round)
+            for (int i = 0; i < ncand; ++i) {
+                const int rows = cand[i];
+                if (lds_bytes(rows, kHalo1, c.pl.rb) > 65536 && lds_bytes(rows, kHalo2, c.pl.rb) > 65536) continue;
+                ctx->tiles.rows1 = lds_bytes(rows, kHalo1, c.pl.rb) <= 65536 ? rows : saved.rows1;
+                ctx->tiles.rows2 = lds_bytes(rows, kHalo2, c.pl.rb) <= 65536 ? rows : saved.rows2;
+                double ms[4];
+                if ((rc = measure(ms)) != LOGFX_OK) break;
+                if (ctx->tiles.rows1 == rows) t1[i] = std::min(t1[i], ms[0]);
+                if (ctx->tiles.rows2 == rows) t2[i] = std::min(t2[i], ms[2]);
+            }
         int r1 = saved.rows1, r2 = saved.rows2;
-        for (int rows : cand) {
-            if (lds_bytes(rows, kHalo1, c.pl.rb) > 65536 && lds_bytes(rows, kHalo2, c.pl.rb) > 65536) continue;
-            ctx->tiles.rows1 = lds_bytes(rows, kHalo1, c.pl.rb) <= 65536 ? rows : saved.rows1;
-            ctx->tiles.rows2 = lds_bytes(rows, kHalo2, c.pl.rb) <= 65536 ? rows : saved.rows2;
-            double ms[4];
-            if ((rc = measure(ms)) != LOGFX_OK) break;
-            if (ctx->tiles.rows1 == rows && ms[0] < best1) best1 = ms[0], r1 = rows;
-            if (ctx->tiles.rows2 == rows && ms[2] < best2) best2 = ms[2], r2 = rows;
+        double best1 = 1e300, best2 = 1e300;
+        for (int i = 0; i < ncand; ++i) {
+            if (t1[i] < best1) best1 = t1[i], r1 = cand[i];
+            if (t2[i] < best2) best2 = t2[i], r2 = cand[i];
         }
         ctx->tiles.rows1 = r1;
         ctx->tiles.rows2 = r2;
         int pe = 0;
         double bestms = 0.0;
         if (rc == LOGFX_OK) {
-            double ms[4];
-            ctx->persistent = false;
-            if ((rc = measure(ms)) == LOGFX_OK) bestms = ms[3];
-            if (rc == LOGFX_OK && n > 1) {
-                ctx->persistent = true;
-                if ((rc = measure(ms)) == LOGFX_OK && ms[3] < bestms) bestms = ms[3], pe = 1;
-            }
+            // batches: one workgroup per tile or a persistent grid, also
+            // round-robin
+            double tp[2] = {1e300, 1e300};
+            for (int round = 0; round < kRounds && rc == LOGFX_OK; ++round)
+                for (int q = 0; q < (n > 1 ? 2 : 1) && rc == LOGFX_OK; ++q) {
+                    double ms[4];
+                    ctx->persistent = q == 1;
+                    if ((rc = measure(ms)) == LOGFX_OK) tp[q] = std::min(tp[q], ms[3]);
+                }
+            pe = tp[1] < tp[0] ? 1 : 0;
+            bestms = tp[pe];
         }
         ctx->timing = saved_t;
         ctx->timed_calls = 0;
