@@ -40,6 +40,13 @@ METRIC = "Mpixel/s full pipeline, % HBM roofline; gated vs plain at >=99.9% agre
 # operation per lane per clock.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# The same lane rate as multiply-adds counted as two operations: MI355X's
+# published FP64 vector peak (78.6 TFLOP/s); the exact int32 path issues its
+# multiply-adds (v_mad_i32_i24, v_dot2_i32_i16 two per lane) at that rate.
+ALU_PEAK_TFLOPS = 2 * VALU_PEAK_TOPS
+# The pipeline's arithmetic per pixel as the method states it: the two
+# direct-form LoG masks of eq. (1), 5x5 and 9x9, 25 + 81 multiply-adds.
+LOG_FMA_PER_PX = 106
 
 # Algorithmic ALU operations per output pixel of the recomputing pass 2
 # (LOGFX_OPT_STORE_Z = 0: LoG and crossings again, then the deviation), counted
@@ -56,20 +63,18 @@ PASS2_OPS = {
     "OR, output bit, store": 3,
 }
 PASS2_OPS_PER_PX = sum(PASS2_OPS.values())
-# Pass 1: the same LoG and zero-crossing work as the pass-2 recompute, plus
-# the per-tile sums (convert, add, multiply-add and count per mask).
-PASS1_OPS_PER_PX = 34 + 21 + 2 * 25 + 2 * 4
 # Pass 2 on stored strengths: the deviation (row sums 5, column sums 4,
 # 9Q - S^2 2, compare 1 per mask), OR, output.
 PASS2Z_OPS_PER_PX = 2 * 12 + 3
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy of known size; profiles/pipeline_kernels_8192x8192_u16.md)
-# for the kernel sources with this hash.  Reported only while the sources are
-# unchanged.
-TRAFFIC_SOURCE_HASH = "f965f10e4e0916f2"
-TRAFFIC_BYTES = {"pass1_kernel": (68995 * 2.0 + 525282 * 1.0) * 1024,
-                 "pass2z_kernel": (296685 * 2.0 + 81738 * 1.0) * 1024}
+# for the kernel sources with this hash and these strip heights.  Reported
+# only while both are unchanged.
+TRAFFIC_SOURCE_HASH = "cd4cf56867698948"
+TRAFFIC_ROWS = [64, 32]
+TRAFFIC_BYTES = {"pass1_kernel": (67857 * 2.0 + 524916 * 1.0) * 1024,
+                 "pass2z_kernel": (313291 * 2.0 + 75329 * 1.0) * 1024}
 # Algorithmic HBM bytes per pixel of each kernel: pass 1 reads the 16-bit
 # image and writes the (Z_1, Z_2) int32 pair; pass 2 reads the pair and
 # writes the output byte.
@@ -211,12 +216,13 @@ def bench_gated(args):
     stream = torch.cuda.current_stream()
     res = {}
     decisions = None
-    if not args.no_tune:   # strip heights for the batch, shared by its three modes
-        tuned = ctx.tune(devs, logfx.Params(*lib_taps, smooth=logfx.SMOOTH_GATE), outs, bits=11, reps=3)
-        res["tuned_batch"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"], "persistent": tuned["persistent"]}
-        log(f"batch tuned: rows {tuned['rows1']}/{tuned['rows2']}, persistent {tuned['persistent']}")
     for name, mode in modes.items():
         params = logfx.Params(*lib_taps, smooth=mode)
+        if not args.no_tune:   # each mode at its own best launch (strip heights, persistence)
+            tuned = ctx.tune(devs, params, outs, bits=11, reps=3)
+            res[f"tuned_{name}"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"],
+                                    "persistent": tuned["persistent"]}
+            log(f"{name} tuned: rows {tuned['rows1']}/{tuned['rows2']}, persistent {tuned['persistent']}")
         _, reps = ctx.extract_batch(devs, params, outs, bits=11, report=True)
         if name == "gated":
             decisions = np.array([r["smoothed"] for r in reps], np.int64)
@@ -260,8 +266,8 @@ def bench_gated(args):
     params = logfx.Params(*lib_taps, smooth=logfx.SMOOTH_GATE, gate_region=T)
     if not args.no_tune:
         tuned = ctx.tune(bands[0], params, [bouts[0]], bits=11, reps=3)
-        res["tuned_seamless"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"]}
-        log(f"seamless tuned: rows {tuned['rows1']}/{tuned['rows2']}")
+        res["tuned_seamless_gated"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"]}
+        log(f"seamless gated tuned: rows {tuned['rows1']}/{tuned['rows2']}")
     seam_dec = []
     for bt, bo in zip(bands, bouts):
         _, rep = ctx.extract(bt, params, bo, bits=11, report=True)
@@ -283,6 +289,10 @@ def bench_gated(args):
     log(f"seamless gated: {ms:.3f} ms/step")
     # the plain always-smoothed form of the same calls, for the gated vs plain comparison
     p_always = logfx.Params(*lib_taps, smooth=logfx.SMOOTH_ALWAYS)
+    if not args.no_tune:
+        tuned = ctx.tune(bands[0], p_always, [bouts[0]], bits=11, reps=3)
+        res["tuned_seamless_always"] = {"rows1": tuned["rows1"], "rows2": tuned["rows2"]}
+        log(f"seamless always tuned: rows {tuned['rows1']}/{tuned['rows2']}")
     for _ in range(args.warmup):
         for bt, bo in zip(bands, bouts):
             ctx.extract(bt, p_always, bo, bits=11)
@@ -348,6 +358,10 @@ def bench_batch(args):
     params = logfx.Params(logfx.make_log_mask(5, 0.8, 16)[0], logfx.make_log_mask(9, 1.4, 16)[0])
     ctx = logfx.Context(0)
     stream = torch.cuda.current_stream()
+    if args.rows:
+        r1, r2 = (int(v) for v in args.rows.split(","))
+        ctx.set_option(logfx.OPT_ROWS1, r1)
+        ctx.set_option(logfx.OPT_ROWS2, r2)
     if not args.no_tune:
         ctx.tune(devs, params, outs, bits=8, reps=3)
 
@@ -411,7 +425,11 @@ def main():
     ap.add_argument("--no-transfers", action="store_true",
                     help="skip the host transfer timing after the timed region")
     ap.add_argument("--no-tune", action="store_true",
-                    help="skip the autotuner (strip heights stay at their defaults)")
+                    help="skip the autotuner (strip heights stay at their defaults, or --rows)")
+    ap.add_argument("--rows", default="",
+                    help="strip heights of pass 1 and pass 2, e.g. 64,32, set before the run of the "
+                         "scene or batch workload (with --no-tune: the launch the tuner picks, "
+                         "without the tuner's own launches in a profile)")
     ap.add_argument("--store-z", type=int, default=1, choices=[0, 1],
                     help="1: pass 2 reads the strengths pass 1 stored (default); 0: recomputes them")
     ap.add_argument("--median-cascade", default="",
@@ -456,6 +474,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuned = None
+    if args.rows:
+        r1, r2 = (int(v) for v in args.rows.split(","))
+        ctx.set_option(logfx.OPT_ROWS1, r1)
+        ctx.set_option(logfx.OPT_ROWS2, r2)
     if not args.no_tune:
         # untimed: pick the strip heights of both passes for this workload
         tuned = ctx.tune(bufs[0], params, [out], bits=11, reps=3)
@@ -603,15 +625,24 @@ def main():
         ops_px = PASS2Z_OPS_PER_PX if stored else PASS2_OPS_PER_PX
     else:
         dom_name = "pass1_kernel"
-        ops_px = PASS1_OPS_PER_PX
-    achieved = ops_px * px / (avg[dom] * 1e-3) / 1e12
+        ops_px = None
+    rows = [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]
+    if dom_name == "pass1_kernel":
+        # the LoG multiply-adds of the method (two operations each) per second
+        # against the ALU peak at that count
+        achieved = 2 * LOG_FMA_PER_PX * px / (avg[dom] * 1e-3) / 1e12
+        peak, unit, work = ALU_PEAK_TFLOPS, "TFLOP/s", f"{LOG_FMA_PER_PX} LoG multiply-adds per pixel"
+    else:
+        achieved = ops_px * px / (avg[dom] * 1e-3) / 1e12
+        peak, unit, work = VALU_PEAK_TOPS, "Tops/s", f"{ops_px} operations per pixel"
     roofline = {
         "bound": "alu", "kernel": dom_name,
-        "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
-        "frac": round(achieved / VALU_PEAK_TOPS, 4),
+        "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": unit,
+        "frac": round(achieved / peak, 4),
         "traffic": (TRAFFIC_BYTES[dom_name] if kernel_source_hash() == TRAFFIC_SOURCE_HASH
-                    and dom_name in TRAFFIC_BYTES and H == 8192 and W == 8192 else None),
-        "ops_per_pixel": ops_px,
+                    and dom_name in TRAFFIC_BYTES and H == 8192 and W == 8192
+                    and rows == TRAFFIC_ROWS else None),
+        "work": work,
         "kernel_hbm": ({"bytes_per_pixel": KERNEL_BYTES_PER_PX[dom_name],
                         "achieved_GBs": round(KERNEL_BYTES_PER_PX[dom_name] * px / (avg[dom] * 1e-3) / 1e9, 1),
                         "frac": round(KERNEL_BYTES_PER_PX[dom_name] * px / (avg[dom] * 1e-3) / 1e9
@@ -627,17 +658,12 @@ def main():
                      "peak_GBs": HBM_PEAK_GBS,
                      "frac": round(3 * px / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
-    if dom_name == "pass1_kernel":
-        # frac above counts the operations of the orbit-sum form the kernel
-        # runs; the same time against the 106 multiply-adds of the two
-        # direct-form masks (25 + 81), the work as eq. (1) states it
-        roofline["frac_direct_form_log_fma"] = round(106 * px / (avg[0] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)
     # why the pipeline cannot sit at 70 % of HBM peak: its arithmetic floor
-    # (pass 1's operations at the VALU peak) against the time its 3 bytes
-    # per pixel take at that fraction of the 8 TB/s
+    # (the LoG multiply-adds alone at the ALU peak) against the time its 3
+    # bytes per pixel take at that fraction of the 8 TB/s
     roofline["hbm_bar"] = {"target_frac": 0.70,
                            "pipeline_frac": roofline["hbm_view"]["frac"],
-                           "alu_floor_ms": round(PASS1_OPS_PER_PX * px / (VALU_PEAK_TOPS * 1e12) * 1e3, 4),
+                           "alu_floor_ms": round(LOG_FMA_PER_PX * px / (VALU_PEAK_TOPS * 1e12) * 1e3, 4),
                            "hbm_time_at_target_ms": round(3 * px / (0.70 * HBM_PEAK_GBS * 1e9) * 1e3, 4)}
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
@@ -649,7 +675,7 @@ def main():
                                "3x3 deviation > 2.0 global; 5x5 hybrid median"
                                + "".join(f", then {m}x{m}" for m in cascade),
                    "pixels": px, "parallelism": "single GPU", "store_z": args.store_z,
-                   "rows_per_strip": [ctx.get_option(logfx.OPT_ROWS1), ctx.get_option(logfx.OPT_ROWS2)]},
+                   "rows_per_strip": rows},
         "kernels_ms": {"pass1": round(avg[0], 4), "finalize": round(avg[1], 4),
                        "pass2": round(avg[2], 4)},
         "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],

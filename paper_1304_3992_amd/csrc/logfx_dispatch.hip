@@ -21,24 +21,27 @@ namespace kern {
 
 // ------------------------------------------------------------- finalize
 // One workgroup per image: fixed-order reduction of the image's tile sums.
-__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
-    __shared__ double sd[4][256];
-    __shared__ long long sc[2][256];
+// 1024 threads, so that the tiles of an 8192^2 image (about 4400) are read
+// in one round of loads.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinalizeArgs a) {
+    __shared__ double sd[4][kFinThreads];
+    __shared__ long long sc[2][kFinThreads];
     const int t = threadIdx.x;
     const int image = blockIdx.x;
     const ImageJob J = job_of(a.L, image);
     double s[4] = {0, 0, 0, 0};
     long long c[2] = {0, 0};
-    // thread t adds tiles t, t + 256, ... in that order; U tiles' loads are
-    // in flight at once (a tile past the end adds zeros, which leaves the
-    // sums unchanged)
+    // thread t adds tiles t, t + kFinThreads, ... in that order; U tiles'
+    // loads are in flight at once (a tile past the end adds zeros, which
+    // leaves the sums unchanged)
     constexpr int U = 8;
-    for (int i0 = t; i0 < J.ntiles1; i0 += 256 * U) {
+    for (int i0 = t; i0 < J.ntiles1; i0 += kFinThreads * U) {
         double v[U][4];
         long long w[U][2];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = i0 + 256 * u;
+            const int i = i0 + kFinThreads * u;
             const long long at = (long long)J.base1 + i;
             const bool in = i < J.ntiles1;
 #pragma unroll
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     sc[0][t] = c[0];
     sc[1][t] = c[1];
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = kFinThreads / 2; off > 0; off >>= 1) {
         if (t < off) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) sd[k][t] += sd[k][t + off];
@@ -139,7 +142,7 @@ hipError_t noalloc_scratch(int device, void **ptr) {
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(kern::finalize_kernel, dim3(a.L.nimg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(kern::finalize_kernel, dim3(a.L.nimg), dim3(kern::kFinThreads), 0, s, a);
     return hipGetLastError();
 }
 
