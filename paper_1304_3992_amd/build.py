@@ -37,6 +37,19 @@ def _units():
     return units
 
 
+def _vgpr_spills(remarks: str) -> list[str]:
+    """Kernels whose resource-usage remarks report spilled vector registers."""
+    out, name = [], None
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:")[1].split()[0]
+        elif "VGPRs Spill:" in line and name:
+            n = int(line.split("VGPRs Spill:")[1].split()[0])
+            if n > 0:
+                out.append(f"{name} ({n})")
+    return out
+
+
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
@@ -46,7 +59,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     while pending or running:
         while pending and len(running) < jobs:
             src, obj, extra = pending.pop(0)
-            cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *extra,
+            # device units report each kernel's register use (spills refused below)
+            remarks = ["-Rpass-analysis=kernel-resource-usage"] if "hip" in extra else []
+            cmd = [hipcc, *HIP_FLAGS, *remarks, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *extra,
                    "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
@@ -54,9 +69,16 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             objs.append(obj)
         p, cmd = running.pop(0)
         err = p.communicate()[1]
-        err = "\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l)
+        spills = _vgpr_spills(err)
+        if p.returncode == 0 and "-Rpass-analysis=kernel-resource-usage" in cmd and "Function Name:" not in err:
+            raise RuntimeError("no kernel resource-usage remarks from " + " ".join(cmd))
+        err = "\n".join(l for l in err.splitlines()
+                        if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l)
         if p.returncode != 0:
             raise RuntimeError("compile failed: " + " ".join(cmd) + "\n" + err)
+        if spills:
+            raise RuntimeError("kernels spill vector registers (their neighbour reads across lanes "
+                               "need every lane's registers intact): " + ", ".join(spills))
         if err.strip() and verbose:
             print(err, flush=True)
     tmp = LIB + ".tmp"

@@ -346,7 +346,11 @@ struct Strip {
         lc = wave * OW + lane + RB + OFF;
         clampL = xc <= 0;
         clampR = xc >= W - 1;
-        outc = lane >= HL && lane < HL + OW && xc < W;
+        // held as one value, so that each use tests it once instead of
+        // re-deriving the lane range
+        int oc = lane >= HL && lane < HL + OW && xc < W;
+        asm("v_mov_b32 %0, %1" : "=v"(oc) : "v"(oc));
+        outc = oc != 0;
     }
 
     // Stage the input rows y0-HL-RB .. (RH rows) and columns from the
@@ -450,13 +454,19 @@ __device__ inline void for_each_tile(int total, F &&f) {
     }
 }
 
+// acc + 1 in the lanes of mask (a wave's ballot): one add with the mask as
+// carry-in
+__device__ inline unsigned add_lanes(unsigned acc, uint64_t mask) {
+    unsigned r;
+    uint64_t co;
+    asm("v_addc_co_u32 %0, %1, 0, %2, %3" : "=v"(r), "=s"(co) : "v"(acc), "s"(mask));
+    return r;
+}
+
 __device__ inline ImageJob job_of(const Launch &L, int image) {
     return L.nimg == 1 ? L.one : L.jobs[image];
 }
 
-// 1 if a crossing strength (never negative) is non-zero, else 0.
-__device__ inline unsigned nonzero(int z) { return min((unsigned)z, 1u); }
-__device__ inline unsigned nonzero(double z) { return z != 0.0 ? 1u : 0u; }
 
 // Storage of the crossing-strength pair of a pixel between the passes: the
 // integer path keeps the exact integer strengths as int32 pairs, the FP64
@@ -481,11 +491,15 @@ template <> struct ZStore<double> {
 
 // ------------------------------------------------------------- pass 1
 // Occupancy: the integer path is held to 128 VGPRs (4 waves per SIMD, the
-// LDS limit); the FP64 path keeps its registers.  The variants that sum the
-// gate's cells, and the persistent variant that stores the strengths, need
-// more and run at 3 waves without spills: a spill reload waits for every
-// outstanding vector memory operation, the strength stores included, and
-// measured slower than the lower occupancy.
+// LDS limit); the FP64 path keeps its registers.  Variants that need more
+// run at fewer waves rather than spill.  No kernel here may spill vector
+// registers (the build refuses one that does): the crossing test reads its
+// neighbours from the adjacent lanes (DPP), and a spill reload that the
+// compiler places under a partial execution mask (a store for the output
+// lanes only) leaves the halo lanes' copies stale, which wrong neighbours
+// then show at the wave borders.  Spills were also slower: a reload waits
+// for every outstanding vector memory operation, the strength stores
+// included.
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
 #ifndef LOGFX_P1_CELL_WAVES
 #define LOGFX_P1_CELL_WAVES 3
@@ -496,10 +510,14 @@ template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4
 template <class Acc, int MODE, bool LOOP>
 constexpr int kPass1Waves =
     !std::is_same<Acc, int>::value ? kMinWaves<Acc>
+    : (MODE & kP1Maps) != 0 ? 2   // inspection only: room for the FP64 map writes
     : (MODE & kP1Packed) != 0 ? ((MODE & kP1Cells) != 0 || LOOP ? 4 : LOGFX_P1_PK_WAVES)
-    : (MODE & kP1Cells) != 0       ? LOGFX_P1_CELL_WAVES
-    : ((MODE & kP1StoreZ) != 0 && LOOP) ? 3
-                                        : kMinWaves<Acc>;
+    : (MODE & kP1Cells) != 0 ? LOGFX_P1_CELL_WAVES
+    : LOOP ? 3
+    : kMinWaves<Acc>;
+// The recomputing pass 2 (the fallback without stored strengths) keeps the
+// LoG rings, the deviation rows and the median rows at once.
+template <class Acc> constexpr int kPass2Waves = std::is_same<Acc, int>::value ? 2 : 1;
 
 // MODE, a set of bits: 0 = statistics only; kP1Maps = also the FP64 maps
 // of a single image; kP1Cells = also the per-cell sums of the gate
@@ -559,38 +577,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     // slot is reused within the tile and the row loop needs no barrier.
     // After the last row one thread per slot adds the slot to the image's
     // cell counters (integer atomics: exact and order-free).
-    unsigned fv = 0, fc = 0;    // value sum; crossings of mask 1 + 2^16 * of mask 2
-    int fcy = 0, fcy0 = 0;      // current cell row; the tile's first
-    int fspan = 0;              // cell rows from the tile's first to its last
-    int fkey0 = 0, fslots = 0;  // the tile's first cell column and its number of cell columns
-    int fslot = 0;              // the slot of the lane's cell column (output lanes)
-    long long fnext = 0;        // first row of the next cell row
-    if constexpr ((MODE & kP1Cells) != 0) {
+    // The row loop keeps one scalar of this bookkeeping, fend (the strip
+    // row that ends the current cell row); the rest is wave-uniform but held
+    // in vector registers (fcy, the slot-row base fat) or recomputed after
+    // the loop, so that the loop's scalar registers do not spill.
+    auto cell_of = [](long long n, int cells, long long d) {
         // floor(n * cells / d) in FP64: exact, since n * cells < 2^53 and a
         // non-integer quotient lies at least 1/d from an integer
-        auto cell_of = [](long long n, int cells, long long d) { return (int)floor((double)n * cells / (double)d); };
+        return (int)floor((double)n * cells / (double)d);
+    };
+    unsigned fv = 0;            // value sum
+    unsigned fc1 = 0, fc2 = 0;  // crossings of mask 1, of mask 2
+    int fcy = 0, fat = 0;       // current cell row (vector register); its slot row's first slot
+    int fslot = 0;              // the slot of the lane's cell column (output lanes)
+    int fend = 0;               // the strip row that ends the current cell row
+    const int flast = g.y0 + g.Rv - 1;
+    // the last row of cell row cy: the first row of cy + 1, less one
+    auto cell_end = [&](const long long cy) __attribute__((always_inline)) {
+        return (int)((((cy + 1) * g.H + (1ll << a.cells_ly) - 1) >> a.cells_ly) - 1);
+    };
+    if constexpr ((MODE & kP1Cells) != 0) {
         const int CX = 1 << a.cells_lx, CY = 1 << a.cells_ly;
-        fkey0 = cell_of(g.x0, CX, g.W);
-        fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, CX, g.W) - fkey0 + 1;
+        const int fkey0 = cell_of(g.x0, CX, g.W);
         fslot = g.outc ? cell_of(g.xc, CX, g.W) - fkey0 : 0;
-        fcy = fcy0 = cell_of(g.y0, CY, g.H);
-        fspan = cell_of(g.y0 + g.Rv - 1, CY, g.H) - fcy0 + 1;
-        fnext = (((long long)fcy + 1) * g.H + CY - 1) >> a.cells_ly;
+        const int fcy0 = cell_of(g.y0, CY, g.H);
+        asm("v_mov_b32 %0, %1" : "=v"(fcy) : "v"(fcy0));
+        fend = min(cell_end(fcy0), flast);
     }
     auto flush = [&](const int r) __attribute__((always_inline)) {
-        if (g.outc && (fv | fc)) {
-            const int at = (fcy - fcy0) * a.cell_slots + fslot;
+        if (g.outc && (fv | fc1 | fc2)) {
+            const int at = fat + fslot;
             atomicAdd(&cellv[at], fv);
-            atomicAdd(&cellc[at], fc);
+            atomicAdd(&cellc[at], fc1 | fc2 << 16);
         }
-        fv = fc = 0;
+        fv = fc1 = fc2 = 0;
         // the cell row of row r + 1 (cells may be empty when H < cells):
         // the first c > fcy whose rows reach past r, by shifts only
         int cy = fcy + 1;
-        const long long CY = 1ll << a.cells_ly;
-        while (((((long long)cy + 1) * g.H + CY - 1) >> a.cells_ly) <= r + 1) ++cy;
+        while (cell_end(cy) < r + 1) ++cy;
+        fat += (cy - fcy) * a.cell_slots;
         fcy = cy;
-        fnext = (((long long)cy + 1) * g.H + CY - 1) >> a.cells_ly;
+        // wave-uniform: the next flush row as a scalar
+        fend = min(__builtin_amdgcn_readfirstlane(cell_end(cy)), flast);
     };
 
     // One step = one new input row.  Full groups of P steps are unrolled so
@@ -653,9 +681,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             // pixel (r, xc): the centre of ring row RB - 1
             if constexpr (PK) fv += as_u32(hp[RB - 1][0]) & 0xFFFFu;
             else fv += (unsigned)h[RB - 1][0];
-            fc += nonzero(zr[0]) + (nonzero(zr[1]) << 16);
-            if (si < 2) fv = fc = 0;
-            else if (r + 1 == fnext || r == g.y0 + g.Rv - 1) flush(r);
+            fc1 = add_lanes(fc1, __ballot(zr[0] != Acc(0)));
+            fc2 = add_lanes(fc2, __ballot(zr[1] != Acc(0)));
+            if (si < 2) fv = fc1 = fc2 = 0;
+            else if (r == fend) flush(r);
         }
     };
     auto run = [&](auto clamp) __attribute__((always_inline)) {
@@ -677,6 +706,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         __syncthreads();
         unsigned long long *fcells =
             a.cells + ((long long)(a.L.nimg == 1 ? 0 : a.L.owner1[item]) << (a.cells_lx + a.cells_ly + 1));
+        const int CX = 1 << a.cells_lx, CY = 1 << a.cells_ly;
+        const int fkey0 = cell_of(g.x0, CX, g.W);
+        const int fslots = cell_of(min(g.x0 + Strip<HL, RB>::TW, g.W) - 1, CX, g.W) - fkey0 + 1;
+        const int fcy0 = cell_of(g.y0, CY, g.H);
+        const int fspan = cell_of(flast, CY, g.H) - fcy0 + 1;
         for (int i = threadIdx.x; i < fspan * fslots; i += blockDim.x) {
             const int cr = i / fslots, cc = i - cr * fslots;
             const unsigned v = cellv[cr * a.cell_slots + cc];
@@ -725,7 +759,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
 // -5 = that window on the images whose med_flags entry is set, none on the
 // others (one kernel; the choice is uniform over a workgroup).
 template <class Acc, int RA, int RB, int MED, bool LOOP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<Acc>))) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass2Waves<Acc>))) void pass2_kernel(Pass2Args<typename AccOps<Acc>::Taps> a) {
     extern __shared__ uint16_t lds[];
     __shared__ int redc[2][8];
     constexpr int HL = kHalo2, P = 2 * RB + 1;
