@@ -117,6 +117,42 @@ def test_packed_and_32bit_forms_agree(ctx, name, make, bits, pair, gb, packed):
     compare(got[1][1], o, smooth=True)
 
 
+def _edge_mask(edge, corner, centre=-65534.0):
+    """A 3x3 D4-symmetric integer mask: centre, 4-neighbour taps, corners."""
+    m = np.full((3, 3), corner, np.float32)
+    m[0, 1] = m[1, 0] = m[1, 2] = m[2, 1] = edge
+    m[1, 1] = centre
+    return m
+
+
+@pytest.mark.parametrize("edge,corner", [(32767.0, -32768.0), (32769.0, -32768.0)],
+                         ids=["int16_limits_packed", "past_int16_32bit"])
+def test_packed_form_at_the_int16_tap_limit(ctx, edge, corner):
+    """Taps at the ends of int16 (packed form, the centre tap in the 24-bit
+    multiply) and just past them (the 32-bit form; an odd tap keeps the grid
+    unit at 1, where an even one would halve every tap), on 11-bit pixels
+    with blocks at 0 and 2047 so that the row-pair sums reach four times the
+    maximum: L and Z bit-identical to the oracle in both forms (which form
+    runs: test_packed_form_selection_logged)."""
+    import torch
+    rng = np.random.default_rng(49)
+    img = rng.integers(0, 2048, (80, 300)).astype(np.uint16)
+    img[10:30, 20:120] = 2047
+    img[40:60, 150:260] = 0
+    img[30:40, :] = (np.indices((10, 300)).sum(0) % 2 * 2047).astype(np.uint16)
+    m1 = _edge_mask(edge, corner)
+    m2 = logfx.make_log_mask(9, 1.4, 16)[0]
+    o = oracle.extract(img, m1.astype(np.float64), oracle.log_mask(9, 1.4, 16)[0], want_intermediates=True)
+    params = logfx.Params(m1, m2)
+    dev = to_device(img)
+    assert logfx.check_params(logfx.image(dev, 11), params) == logfx.PATH_INT32
+    maps = ctx.extract_maps(dev, params, bits=11)
+    torch.cuda.synchronize()
+    for k in ("L1", "L2", "Z1", "Z2"):
+        g = maps[k].cpu().numpy()
+        assert np.array_equal(g, o[k]), (k, int((g != o[k]).sum()))
+
+
 SELECTION_SCRIPT = r"""
 import sys
 sys.path.insert(0, %r)
@@ -126,12 +162,19 @@ from paper_1304_3992_amd import logfx
 from parity import masks, to_device
 ctx = logfx.Context(0)
 rng = np.random.default_rng(47)
-cases = [(rng.integers(0, 2048, (40, 70)).astype(np.uint16), 11, 16, 1),
-         (rng.integers(0, 2048, (41, 70)).astype(np.uint16), 11, 16, 0),
-         (rng.integers(0, 16384, (42, 70)).astype(np.uint16), 14, 12, 1)]
-for img, bits, gb, form in cases:
+def edge(e):
+    m = np.full((3, 3), -32768.0, np.float32)
+    m[0, 1] = m[1, 0] = m[1, 2] = m[2, 1] = e
+    m[1, 1] = -65534.0
+    return m
+cases = [(rng.integers(0, 2048, (40, 70)).astype(np.uint16), 11, masks(grid_bits=16)[1], 1),
+         (rng.integers(0, 2048, (41, 70)).astype(np.uint16), 11, masks(grid_bits=16)[1], 0),
+         (rng.integers(0, 16384, (42, 70)).astype(np.uint16), 14, masks(grid_bits=12)[1], 1),
+         (rng.integers(0, 2048, (43, 70)).astype(np.uint16), 11, (edge(32767.0), masks()[1][1]), 1),
+         (rng.integers(0, 2048, (44, 70)).astype(np.uint16), 11, (edge(32769.0), masks()[1][1]), 1)]
+for img, bits, taps, form in cases:
     ctx.set_option(logfx.OPT_PACKED_LOG, form)
-    ctx.extract(to_device(img), logfx.Params(*masks(grid_bits=gb)[1]), bits=bits)
+    ctx.extract(to_device(img), logfx.Params(*taps), bits=bits)
     torch.cuda.synchronize()
 print("done")
 """
@@ -140,8 +183,8 @@ print("done")
 def test_packed_form_selection_logged():
     """Which form runs, as the call log states it (a child process: the
     log setting is read once): packed for 11-bit pixels, the 32-bit form
-    when the option turns it off, and for 14-bit pixels whatever the
-    option says."""
+    when the option turns it off, for 14-bit pixels whatever the option
+    says, and at the int16 limit of the non-centre taps."""
     import subprocess
     import sys
     here = os.path.dirname(os.path.abspath(__file__))
@@ -150,10 +193,12 @@ def test_packed_form_selection_logged():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "done" in r.stdout, r.stderr[-2000:]
     lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[liblogfx] extract:")]
-    assert len(lines) == 3, r.stderr[-2000:]
+    assert len(lines) == 5, r.stderr[-2000:]
     assert "40 x 70, int32 (packed) path" in lines[0]
     assert "41 x 70, int32 path" in lines[1]
     assert "42 x 70, int32 path" in lines[2]
+    assert "43 x 70, int32 (packed) path" in lines[3]   # non-centre taps 32767 and -32768
+    assert "44 x 70, int32 path" in lines[4]            # one at 32769
 
 
 EXTRACT_CASES = [
