@@ -33,6 +33,19 @@ constexpr int kOffWf = kOffB3 + kC3;
 constexpr int kOffBf = kOffWf + kC3;
 constexpr int kNParam = kOffBf + 1;          // 14369
 
+// The bfloat16 copy of the parameters holds the flat vector and after it,
+// for the forward kernels, each convolution's weights again as
+// [co][tap * cip + ci] rows of perm_row(CI) entries: cip = CI rounded up to
+// a multiple of 4, the row rounded up to whole 16-deep reduction blocks
+// plus 8 (so that rows start 2 (mod 4) 8-byte words apart); the padding
+// entries are zero.
+constexpr int perm_cip(int ci) { return (ci + 3) / 4 * 4; }
+constexpr int perm_row(int ci) { return (9 * perm_cip(ci) + 15) / 16 * 16 + 8; }
+constexpr int kPermW1 = (kNParam + 7) / 8 * 8;
+constexpr int kPermW2 = kPermW1 + kC1 * perm_row(kC0);
+constexpr int kPermW3 = kPermW2 + kC2 * perm_row(kC1);
+constexpr int kWbfElems = kPermW3 + kC3 * perm_row(kC2);
+
 // Per-cell sums that pass 1 accumulates for every image (feature mode):
 // [image][2][kCellCount] (or [2][gy kCells][gx kCells] for one image whose
 // gx x gy regions the gate decides one by one) of
@@ -47,7 +60,7 @@ struct CellSink {
 struct NetBuffers {
     const uint16_t *x0;      // features [N][3][128][128] (indexed through idx)
     const int *idx;          // [B] sample of each batch row, or nullptr (row b = sample b)
-    const uint16_t *w;       // bfloat16 copy of the parameter vector
+    const uint16_t *w;       // bfloat16 copy of the parameters (kWbfElems entries)
     const float *theta;      // FP32 parameters (biases, head)
     uint16_t *a1, *a2, *a3;  // ReLU outputs
     uint16_t *g1, *g2, *g3;  // masked gradients w.r.t. the pre-activations
@@ -71,7 +84,7 @@ long long partial_elems(int B);
 struct AdamArgs {
     float *theta, *m, *v;
     const float *grad;
-    uint16_t *wbf;        // refreshed bfloat16 copy
+    uint16_t *wbf;        // refreshed bfloat16 copy (kWbfElems: flat, then the forward layout)
     float lr, beta1, beta2, eps, wd, bc1, bc2;   // bc = 1 - beta^t
     int n;
 };
@@ -82,12 +95,13 @@ hipError_t launch_zero_cells(unsigned long long *cells, long long nsets, hipStre
 // the cell sums (gx x gy regions per image, 1 x 1 for whole images).
 hipError_t launch_finish_features(const Launch &L, const unsigned long long *cells, double maxval,
                                   uint16_t *feats, int gx, int gy, hipStream_t s);
-hipError_t launch_forward(const NetBuffers &n, hipStream_t s);
+// The logits of the batch and, for non-null flags / decisions, the
+// decisions flags[b] = decisions[b] = logits[b] > 0.
+hipError_t launch_forward(const NetBuffers &n, hipStream_t s, int *flags = nullptr, uint8_t *decisions = nullptr);
 hipError_t launch_backward(const NetBuffers &n, hipStream_t s);   // after launch_forward
 hipError_t launch_adamw(const AdamArgs &a, hipStream_t s);
-hipError_t launch_to_bf16(const float *src, uint16_t *dst, int n, hipStream_t s);
-// flags[i] = logits[i] > 0
-hipError_t launch_decide(const float *logits, int *flags, uint8_t *decisions, int n, hipStream_t s);
+// wbf (kWbfElems, its padding already zero) from the FP32 parameters.
+hipError_t launch_params_to_bf16(const float *theta, uint16_t *wbf, hipStream_t s);
 
 }  // namespace gate
 }  // namespace logfx

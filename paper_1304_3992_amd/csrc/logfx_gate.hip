@@ -5,9 +5,10 @@
 // Network: three 3x3 convolutions of stride 2 with zero padding
 // (3 -> 16 -> 32 -> 32 channels, 128 -> 64 -> 32 -> 16), ReLU after each,
 // global average pooling and a linear layer to one logit.  The convolutions
-// run as implicit GEMMs on v_mfma_f32_16x16x16_bf16: bfloat16 operands
-// gathered straight from the activation maps, FP32 accumulation, one wave
-// per 16 x (all output channels) block.  Stored activations and their
+// run as implicit GEMMs on v_mfma_f32_16x16x16_bf16 with FP32 accumulation:
+// forward, a workgroup stages its input rows and the weights in LDS; the
+// backward kernels gather their operands from the activation maps, one
+// wave per 16 x (all channels) block.  Stored activations and their
 // gradients are bfloat16; biases, the head, the loss and AdamW are FP32.
 // Every reduction has a fixed order (split-K partials are summed in split
 // order, no float atomics), so a training step is deterministic.
@@ -47,54 +48,126 @@ struct Geo {
 // ---------------------------------------------------------------- forward
 // out[b][co][p] = bf16(relu(bias[co] + sum_{ci,ky,kx} w[co][ci][ky][kx] in[b][ci][2oy+ky-1][2ox+kx-1]))
 // for output pixel p = (oy, ox).  GEMM rows = co, columns = 16 pixels of one
-// image, reduction over (ci, ky, kx).  A wave takes PW consecutive blocks of
-// 16 pixels of one image: each weight fragment is loaded once for the PW
-// products that use it.
-template <int CI, int CO, int HI, int PW>
+// output row, reduction over k = (tap, ci), tap = 3 ky + kx, channels
+// padded to a multiple of four (CI = 3 -> 4, with zero weights).
+//
+// A workgroup takes TH output rows of one image.  It first stages in LDS
+// the 2 TH + 1 input rows they read, channel-innermost (one 8-byte slot per
+// four channels of a pixel, column -1 and row -1 as the zero padding), and
+// copies the layer's weights, kept in that [co][k] order beside the flat
+// parameters, as they are; a lane's four reduction indices of a
+// 16-deep block are then four consecutive channels at one tap, so each
+// MFMA operand is one 8-byte LDS read.  Neighbouring lanes of an operand
+// read pixels two apart (an odd number of slots per pixel) or weight rows
+// 2 (mod 4) words apart, so the 32 lanes of a half-wave hit distinct banks.  Each of the four waves computes PW
+// blocks of 16 pixels for all output channels.
+template <int CI, int HI, int TH>
+struct Stage {
+    static constexpr int CIP = perm_cip(CI);            // padded channels
+    static constexpr int G4 = CIP / 4;                  // four-channel groups per pixel
+    static constexpr int P = G4 % 2 ? G4 : G4 + 1;      // 8-byte slots per pixel
+    static constexpr int X = HI + 1;                    // columns -1 .. HI-1
+    static constexpr int R = 2 * TH + 1;                // input rows of TH output rows
+    static constexpr int KB = (9 * CIP + 15) / 16;      // 16-deep reduction blocks
+    static constexpr int KROW = perm_row(CI);           // weight row: KB * 16 + 8
+    static_assert(KROW == KB * 16 + 8, "weight row of the forward layout");
+};
+
+template <int CI, int CO, int HI, int TH>
 __global__ __launch_bounds__(256) void conv_fwd(const uint16_t *__restrict__ in, const int *__restrict__ idx,
                                                 const uint16_t *__restrict__ w, const float *__restrict__ bias,
                                                 uint16_t *__restrict__ out, int B) {
     using G = Geo<CI, CO, HI>;
-    constexpr int PB = G::HWO / 16;   // 16-pixel blocks per image
-    static_assert(PB % PW == 0, "whole blocks per wave");
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / 64);
-    if (wave >= B * (PB / PW)) return;
-    const int b = wave / (PB / PW), pb0 = (wave % (PB / PW)) * PW;
-    const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
+    using S = Stage<CI, HI, TH>;
+    constexpr int HO = G::HO, BR = HO / 16, NB = TH * BR, PW = NB / 4, TILES = HO / TH;
+    static_assert(HO % TH == 0 && NB % 4 == 0 && HI % 4 == 0, "tile shape");
+    typedef uint32_t u32x2a2 __attribute__((ext_vector_type(2), aligned(2)));
+    __shared__ uint2 xs[S::R * S::X * S::P];
+    __shared__ __align__(16) uint16_t ws[CO * S::KROW];
+    const int b = blockIdx.x / TILES, oy0 = (blockIdx.x % TILES) * TH;
+    if (b >= B) return;   // uniform over the workgroup
+    const int t = threadIdx.x;
     const uint16_t *ib = in + (long long)(idx ? idx[b] : b) * CI * G::HWI;
+
+    // Input rows 2 oy0 - 1 .. 2 oy0 + 2 TH - 1: four pixels of four channels
+    // per item, read as one 8-byte word per channel and written as four
+    // slots; the weights in 16-byte chunks.  All reads are issued before
+    // the first LDS write.
+    constexpr int XQ = HI / 4, NI = S::R * S::G4 * XQ, UI = (NI + 255) / 256;
+    constexpr int NW = CO * S::KROW / 8, UW = (NW + 255) / 256;
+    static_assert((CO * S::KROW) % 8 == 0, "weights in 8-element chunks");
+    uint32_t v[UI][4][2];
+    uint4 wc[UW];
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+        const int it = t + 256 * u, xq = it % XQ, rg = it / XQ, g = rg % S::G4, r = rg / S::G4;
+        const int iy = 2 * oy0 - 1 + r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ch = 4 * g + j;
+            if (it < NI && ch < CI && iy >= 0) {
+                const u32x2a2 x = *reinterpret_cast<const u32x2a2 *>(ib + ch * G::HWI + iy * HI + 4 * xq);
+                v[u][j][0] = x.x;
+                v[u][j][1] = x.y;
+            } else {
+                v[u][j][0] = v[u][j][1] = 0u;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+        const int it = t + 256 * u;
+        wc[u] = it < NW ? reinterpret_cast<const uint4 *>(w)[it] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+        const int it = t + 256 * u, xq = it % XQ, rg = it / XQ, g = rg % S::G4, r = rg / S::G4;
+        if (it >= NI) break;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int sh = 16 * (p & 1), wd = p >> 1;
+            const uint32_t c0 = (v[u][0][wd] >> sh) & 0xFFFFu, c1 = (v[u][1][wd] >> sh) & 0xFFFFu;
+            const uint32_t c2 = (v[u][2][wd] >> sh) & 0xFFFFu, c3 = (v[u][3][wd] >> sh) & 0xFFFFu;
+            xs[(r * S::X + 4 * xq + p + 1) * S::P + g] = make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
+        }
+    }
+    for (int it = t; it < S::R * S::G4; it += 256)
+        xs[(it / S::G4) * S::X * S::P + it % S::G4] = make_uint2(0u, 0u);
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+        const int it = t + 256 * u;
+        if (it < NW) reinterpret_cast<uint4 *>(ws)[it] = wc[u];
+    }
+    __syncthreads();
+
+    const int wv = t >> 6, l = t & 63, q = l >> 4, c = l & 15;
     f32x4 acc[G::MB][PW];
 #pragma unroll
     for (int mb = 0; mb < G::MB; ++mb)
 #pragma unroll
         for (int j = 0; j < PW; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < G::KP; kb += 16) {
+    for (int kb = 0; kb < S::KB; ++kb) {
+        const int k0 = 16 * kb + 4 * q;   // the lane's four reduction indices: k0 .. k0 + 3
+        const int tap = k0 / S::CIP, g = (k0 - tap * S::CIP) >> 2;
+        const int tc = tap < 9 ? tap : 0, ky = tc / 3, kx = tc - 3 * ky;
         bf16x4 av[G::MB];
 #pragma unroll
         for (int mb = 0; mb < G::MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = kb + 4 * q + i;
-                av[mb][i] = k < G::K ? (short)w[(mb * 16 + c) * G::K + k] : (short)0;
-            }
+            av[mb] = *reinterpret_cast<const bf16x4 *>(ws + (mb * 16 + c) * S::KROW + k0);
 #pragma unroll
         for (int j = 0; j < PW; ++j) {
-            const int p = (pb0 + j) * 16 + c, oy = p / G::HO, ox = p % G::HO;
-            bf16x4 bv;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = kb + 4 * q + i;
-                const int ci = k / 9, t = k - 9 * ci, ky = t / 3, kx = t - 3 * ky;
-                const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;   // < HI always
-                bv[i] = (k < G::K && iy >= 0 && ix >= 0) ? (short)ib[ci * G::HWI + iy * HI + ix] : (short)0;
-            }
+            const int blk = wv * PW + j, row = blk / BR, ox = (blk % BR) * 16 + c;
+            bf16x4 bv = *reinterpret_cast<const bf16x4 *>(xs + ((2 * row + ky) * S::X + 2 * ox + kx) * S::P + g);
+            if (tap >= 9) bv = bf16x4{0, 0, 0, 0};
 #pragma unroll
             for (int mb = 0; mb < G::MB; ++mb) acc[mb][j] = mfma(av[mb], bv, acc[mb][j]);
         }
     }
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
-        const int p = (pb0 + j) * 16 + c;
+        const int blk = wv * PW + j;
+        const int p = (oy0 + blk / BR) * HO + (blk % BR) * 16 + c;
 #pragma unroll
         for (int mb = 0; mb < G::MB; ++mb)
 #pragma unroll
@@ -105,23 +178,47 @@ __global__ __launch_bounds__(256) void conv_fwd(const uint16_t *__restrict__ in,
     }
 }
 
-// gap[b][c] = mean of a3[b][c]; z[b] = sum_c gap[b][c] wf[c] + bf
-__global__ __launch_bounds__(64) void head_fwd(const uint16_t *__restrict__ a3, const float *__restrict__ theta,
-                                              float *__restrict__ gap, float *__restrict__ logits) {
+// gap[b][c] = mean of a3[b][c]; z[b] = sum_c gap[b][c] wf[c] + bf, and,
+// where asked for, the decision z[b] > 0 as flags[b] / decisions[b].  Eight
+// lanes per channel, 32 positions each; the lane sums are combined by a
+// butterfly, so the order is fixed and every lane of the eight holds the
+// same total.
+__global__ __launch_bounds__(256) void head_fwd(const uint16_t *__restrict__ a3, const float *__restrict__ theta,
+                                               float *__restrict__ gap, float *__restrict__ logits,
+                                               int *__restrict__ flags, uint8_t *__restrict__ decisions) {
     constexpr int HW = kH3 * kH3;
-    const int b = blockIdx.x, c = threadIdx.x;
-    float g = 0.0f;
-    if (c < kC3) {
-        const uint16_t *p = a3 + ((long long)b * kC3 + c) * HW;
-        float s = 0.0f;
-        for (int i = 0; i < HW; ++i) s += from_bf16(p[i]);
-        g = s / (float)HW;
-        gap[b * kC3 + c] = g;
-    }
-    float t = c < kC3 ? g * theta[kOffWf + c] : 0.0f;
+    static_assert(kC3 * 8 == 256 && HW == 8 * 32, "eight lanes of 32 positions per channel");
+    typedef uint32_t u32x4a2 __attribute__((ext_vector_type(4), aligned(2)));
+    __shared__ float part[kC3];
+    const int b = blockIdx.x, t = threadIdx.x, ch = t >> 3;
+    const uint16_t *p = a3 + ((long long)b * kC3 + ch) * HW + (t & 7) * 32;
+    float s = 0.0f;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-    if (c == 0) logits[b] = t + theta[kOffBf];
+    for (int v = 0; v < 4; ++v) {
+        const u32x4a2 u = *reinterpret_cast<const u32x4a2 *>(p + 8 * v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s += __uint_as_float(u[e] << 16) + __uint_as_float(u[e] & 0xFFFF0000u);
+    }
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    const float g = s / (float)HW;
+    if ((t & 7) == 0) {
+        gap[b * kC3 + ch] = g;
+        part[ch] = g * theta[kOffWf + ch];
+    }
+    __syncthreads();
+    if (t < 64) {
+        float z = t < kC3 ? part[t] : 0.0f;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off);
+        if (t == 0) {
+            z += theta[kOffBf];
+            logits[b] = z;
+            if (flags) flags[b] = z > 0.0f;
+            if (decisions) decisions[b] = (uint8_t)(z > 0.0f);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- backward
@@ -279,6 +376,20 @@ __global__ __launch_bounds__(256) void reduce_weight(const float *__restrict__ p
 }
 
 // ---------------------------------------------------------------- AdamW
+// Index in the bfloat16 copy of parameter i's second place, in the forward
+// layout of its convolution's weights, or -1 for biases and the head.
+template <int CI>
+__device__ inline int forward_at_layer(int n, int perm) {
+    const int co = n / (CI * 9), k = n - co * CI * 9, ci = k / 9, tap = k - 9 * ci;
+    return perm + co * perm_row(CI) + tap * perm_cip(CI) + ci;
+}
+__device__ inline int forward_at(int i) {
+    if (i >= kOffW1 && i < kOffB1) return forward_at_layer<kC0>(i - kOffW1, kPermW1);
+    if (i >= kOffW2 && i < kOffB2) return forward_at_layer<kC1>(i - kOffW2, kPermW2);
+    if (i >= kOffW3 && i < kOffB3) return forward_at_layer<kC2>(i - kOffW3, kPermW3);
+    return -1;
+}
+
 // Decoupled weight decay on every parameter; refreshes the bfloat16 copy.
 __global__ __launch_bounds__(256) void adamw(AdamArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,12 +402,19 @@ __global__ __launch_bounds__(256) void adamw(AdamArgs a) {
     const float p = a.theta[i];
     const float np = p - a.lr * ((m / a.bc1) / (sqrtf(v / a.bc2) + a.eps) + a.wd * p);
     a.theta[i] = np;
-    a.wbf[i] = to_bf16(np);
+    const uint16_t h = to_bf16(np);
+    a.wbf[i] = h;
+    const int j = forward_at(i);
+    if (j >= 0) a.wbf[j] = h;
 }
 
-__global__ __launch_bounds__(256) void to_bf16_kernel(const float *src, uint16_t *dst, int n) {
+__global__ __launch_bounds__(256) void params_to_bf16(const float *theta, uint16_t *wbf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = to_bf16(src[i]);
+    if (i >= kNParam) return;
+    const uint16_t h = to_bf16(theta[i]);
+    wbf[i] = h;
+    const int j = forward_at(i);
+    if (j >= 0) wbf[j] = h;
 }
 
 // ---------------------------------------------------------------- features
@@ -310,53 +428,67 @@ __device__ inline long long cell_span(long long c, long long n, long long cells)
 // image blockIdx.y / (gx gy) and, within it, region blockIdx.y % (gx gy)
 // (row-major, gx regions per row) of kCells x kCells cells; the image's
 // cell grid is gy kCells rows by gx kCells columns (gx = gy = 1: the whole
-// image).
+// image).  A workgroup takes kFinRows cell rows of one set; the cell
+// spans of its rows and columns (64-bit divisions) are computed once into
+// LDS.
+constexpr int kFinRows = 16;
 __global__ __launch_bounds__(256) void finish_features(Launch L, const unsigned long long *__restrict__ cells,
                                                        double maxval, uint16_t *__restrict__ feats, int gx,
                                                        int gy) {
+    static_assert(kCells + kFinRows <= 256 && kCells % kFinRows == 0, "spans of one workgroup");
+    __shared__ long long span_x[kCells], span_y[kFinRows];
     const int set = blockIdx.y, nreg = gx * gy;
     const int img = set / nreg, reg = set - img * nreg;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kCellCount) return;
     const ImageJob &J = L.nimg == 1 ? L.one : L.jobs[img];
     const long long CX = (long long)gx * kCells, CY = (long long)gy * kCells;
-    const long long cy = (long long)(reg / gx) * kCells + i / kCells;
-    const long long cx = (long long)(reg % gx) * kCells + i % kCells;
-    const long long area = cell_span(cy, J.img.H, CY) * cell_span(cx, J.img.W, CX);
-    const unsigned long long *cs = cells + (long long)img * 2 * CX * CY + cy * CX + cx;
-    uint16_t *f = feats + (long long)set * kFeatC * kCellCount;
-    if (area <= 0) {
-        f[i] = f[kCellCount + i] = f[2 * kCellCount + i] = 0;
-        return;
+    const int r0 = blockIdx.x * kFinRows;
+    const long long cy0 = (long long)(reg / gx) * kCells + r0, cx0 = (long long)(reg % gx) * kCells;
+    const int t = threadIdx.x;
+    const unsigned long long *cs0 = cells + (long long)img * 2 * CX * CY + cy0 * CX + cx0;
+    uint16_t *f = feats + (long long)set * kFeatC * kCellCount + r0 * kCells;
+    // every cell's two sums are loaded before the spans and the first use
+    constexpr int U = kFinRows * kCells / 256;
+    static_assert(U * 256 == kFinRows * kCells, "whole cells per thread");
+    unsigned long long sv[U], zz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = t + 256 * u, r = j / kCells, x = j - r * kCells;
+        sv[u] = cs0[r * CX + x];
+        zz[u] = cs0[CX * CY + r * CX + x];
     }
-    const double ar = (double)area;
-    const unsigned long long zz = cs[CX * CY];
-    f[i] = to_bf16((float)(((double)cs[0] / ar) / maxval));
-    f[kCellCount + i] = to_bf16((float)((double)(zz & 0xFFFFFFFFull) / ar));
-    f[2 * kCellCount + i] = to_bf16((float)((double)(zz >> 32) / ar));
+    if (t < kCells) span_x[t] = cell_span(cx0 + t, J.img.W, CX);
+    else if (t < kCells + kFinRows) span_y[t - kCells] = cell_span(cy0 + (t - kCells), J.img.H, CY);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = t + 256 * u, r = j / kCells, x = j - r * kCells;
+        const long long area = span_y[r] * span_x[x];
+        uint16_t f0 = 0, f1 = 0, f2 = 0;
+        if (area > 0) {
+            const double ar = (double)area;
+            f0 = to_bf16((float)(((double)sv[u] / ar) / maxval));
+            f1 = to_bf16((float)((double)(zz[u] & 0xFFFFFFFFull) / ar));
+            f2 = to_bf16((float)((double)(zz[u] >> 32) / ar));
+        }
+        f[j] = f0;
+        f[kCellCount + j] = f1;
+        f[2 * kCellCount + j] = f2;
+    }
 }
 
-__global__ __launch_bounds__(256) void zero_u64(unsigned long long *p, long long n) {
+// Clears n2 16-byte words (the cell sums: two per pair of cells).
+__global__ __launch_bounds__(256) void zero_cells(ulonglong2 *p, long long n2) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-__global__ __launch_bounds__(256) void decide(const float *logits, int *flags, uint8_t *decisions, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int d = logits[i] > 0.0f;
-    if (flags) flags[i] = d;
-    if (decisions) decisions[i] = (uint8_t)d;
+    if (i < n2) p[i] = make_ulonglong2(0ull, 0ull);
 }
 
 inline unsigned blocks(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <int CI, int CO, int HI, int PW>
+template <int CI, int CO, int HI, int TH>
 hipError_t fwd(const uint16_t *in, const int *idx, const uint16_t *w, const float *bias, uint16_t *out, int B,
                hipStream_t s) {
-    using G = Geo<CI, CO, HI>;
-    hipLaunchKernelGGL((conv_fwd<CI, CO, HI, PW>), dim3(blocks((long long)B * (G::HWO / 16 / PW), 4)), dim3(256), 0, s,
-                       in, idx, w, bias, out, B);
+    hipLaunchKernelGGL((conv_fwd<CI, CO, HI, TH>), dim3((unsigned)B * (HI / 2 / TH)), dim3(256), 0, s, in, idx, w,
+                       bias, out, B);
     return hipGetLastError();
 }
 
@@ -392,23 +524,28 @@ long long partial_elems(int B) {
 
 hipError_t launch_zero_cells(unsigned long long *cells, long long nsets, hipStream_t s) {
     const long long n = nsets * 2 * kCellCount;
-    hipLaunchKernelGGL(zero_u64, dim3(blocks(n, 256)), dim3(256), 0, s, cells, n);
+    static_assert(kCellCount % 2 == 0, "cell sums in 16-byte words");
+    hipLaunchKernelGGL(zero_cells, dim3(blocks(n / 2, 256)), dim3(256), 0, s, reinterpret_cast<ulonglong2 *>(cells),
+                       n / 2);
     return hipGetLastError();
 }
 
 hipError_t launch_finish_features(const Launch &L, const unsigned long long *cells, double maxval, uint16_t *feats,
                                   int gx, int gy, hipStream_t s) {
-    hipLaunchKernelGGL(finish_features, dim3(blocks(kCellCount, 256), L.nimg * gx * gy), dim3(256), 0, s, L, cells,
-                       maxval, feats, gx, gy);
+    hipLaunchKernelGGL(finish_features, dim3(kCells / kFinRows, L.nimg * gx * gy), dim3(256), 0, s, L, cells, maxval,
+                       feats, gx, gy);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const NetBuffers &n, hipStream_t s) {
+hipError_t launch_forward(const NetBuffers &n, hipStream_t s, int *flags, uint8_t *decisions) {
+    // conv_fwd copies each layer's weights in 16-byte chunks
+    static_assert(kPermW1 % 8 == 0 && kPermW2 % 8 == 0 && kPermW3 % 8 == 0, "weight offsets");
     hipError_t e;
-    if ((e = fwd<kC0, kC1, kH0, 4>(n.x0, n.idx, n.w + kOffW1, n.theta + kOffB1, n.a1, n.B, s)) != hipSuccess) return e;
-    if ((e = fwd<kC1, kC2, kH1, 4>(n.a1, nullptr, n.w + kOffW2, n.theta + kOffB2, n.a2, n.B, s)) != hipSuccess) return e;
-    if ((e = fwd<kC2, kC3, kH2, 2>(n.a2, nullptr, n.w + kOffW3, n.theta + kOffB3, n.a3, n.B, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(head_fwd, dim3(n.B), dim3(64), 0, s, n.a3, n.theta, n.gap, n.logits);
+    // output rows per workgroup: 4, 4, 8 (measured against 8, 8 and 4, 16)
+    if ((e = fwd<kC0, kC1, kH0, 4>(n.x0, n.idx, n.w + kPermW1, n.theta + kOffB1, n.a1, n.B, s)) != hipSuccess) return e;
+    if ((e = fwd<kC1, kC2, kH1, 4>(n.a1, nullptr, n.w + kPermW2, n.theta + kOffB2, n.a2, n.B, s)) != hipSuccess) return e;
+    if ((e = fwd<kC2, kC3, kH2, 8>(n.a2, nullptr, n.w + kPermW3, n.theta + kOffB3, n.a3, n.B, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(head_fwd, dim3(n.B), dim3(256), 0, s, n.a3, n.theta, n.gap, n.logits, flags, decisions);
     return hipGetLastError();
 }
 
@@ -433,13 +570,8 @@ hipError_t launch_adamw(const AdamArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_to_bf16(const float *src, uint16_t *dst, int n, hipStream_t s) {
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, src, dst, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_decide(const float *logits, int *flags, uint8_t *decisions, int n, hipStream_t s) {
-    hipLaunchKernelGGL(decide, dim3(blocks(n, 256)), dim3(256), 0, s, logits, flags, decisions, n);
+hipError_t launch_params_to_bf16(const float *theta, uint16_t *wbf, hipStream_t s) {
+    hipLaunchKernelGGL(params_to_bf16, dim3(blocks(kNParam, 256)), dim3(256), 0, s, theta, wbf);
     return hipGetLastError();
 }
 

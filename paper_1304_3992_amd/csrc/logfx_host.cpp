@@ -255,9 +255,16 @@ int ensure_gate_params(logfx_ctx *ctx) {
     if ((rc = realloc_dev(ctx, G.m, gate::kNParam)) != LOGFX_OK ||
         (rc = realloc_dev(ctx, G.v, gate::kNParam)) != LOGFX_OK ||
         (rc = realloc_dev(ctx, G.grad, gate::kNParam)) != LOGFX_OK ||
-        (rc = realloc_dev(ctx, G.wbf, gate::kNParam)) != LOGFX_OK ||
+        (rc = realloc_dev(ctx, G.wbf, gate::kWbfElems)) != LOGFX_OK ||
         (rc = realloc_dev(ctx, G.theta, gate::kNParam)) != LOGFX_OK)
         return rc;
+    // the padding of the forward weight layout stays zero
+    const hipError_t e = hipMemset(G.wbf, 0, sizeof(uint16_t) * gate::kWbfElems);
+    if (e != hipSuccess) {
+        (void)hipFree(G.theta);
+        G.theta = nullptr;
+        return hip_err(ctx, e, "gate parameters");
+    }
     return LOGFX_OK;
 }
 
@@ -869,15 +876,13 @@ hipError_t launch_all(const Launches &k, hipStream_t s, hipEvent_t *ev, int unti
     if (until < UNTIL_OUTPUT) {   // the gate alone: no thresholds needed
         if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, k.gx, k.gy, s)) != hipSuccess) return e;
         if (until == UNTIL_FEATURES) return hipSuccess;
-        if ((e = gate::launch_forward(k.net, s)) != hipSuccess) return e;
-        return gate::launch_decide(k.net.logits, k.flags, k.decisions, k.nsets, s);
+        return gate::launch_forward(k.net, s, k.flags, k.decisions);
     }
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if ((e = launch_finalize(k.fin, s)) != hipSuccess) return e;
     if (k.gated) {
         if ((e = gate::launch_finish_features(k.fin.L, k.cells, k.maxval, k.feats, k.gx, k.gy, s)) != hipSuccess ||
-            (e = gate::launch_forward(k.net, s)) != hipSuccess ||
-            (e = gate::launch_decide(k.net.logits, k.flags, k.decisions, k.nsets, s)) != hipSuccess)
+            (e = gate::launch_forward(k.net, s, k.flags, k.decisions)) != hipSuccess)
             return e;
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -1560,7 +1565,7 @@ int logfx_gate_set_params(logfx_ctx *ctx, const float *theta, int64_t n) {
     hipError_t e;
     if ((e = hipMemcpy(G.theta, theta, bytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(G.m, 0, bytes)) != hipSuccess || (e = hipMemset(G.v, 0, bytes)) != hipSuccess ||
-        (e = gate::launch_to_bf16(G.theta, G.wbf, gate::kNParam, nullptr)) != hipSuccess ||
+        (e = gate::launch_params_to_bf16(G.theta, G.wbf, nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess)
         return hip_err(ctx, e, "gate parameters");
     G.step = 0;

@@ -17,15 +17,18 @@
 // output tile of kTileWaves wave-wide column strips side by side, `rows`
 // rows tall; the input tile plus halo is staged once in LDS as u16 with
 // clamp-to-edge coordinates.  Each lane owns one column and walks down the
-// rows, keeping a ring of 2R+1 rows of horizontal pair sums in registers.
+// rows, keeping a ring of 2R+1 rows of horizontal pair sums in registers
+// (32-bit, or packed 16-bit pairs in the integer path's packed form).
 // Horizontal neighbours of later stages come from the adjacent lanes (DPP
 // wave shifts on the vector ALU; lanes at the image border take their own
 // value).
 //
 // Exactness.  Mask taps are integers k on a power-of-two grid, and the LoG
-// is evaluated on D4 orbit sums of pixels: L = sum_o k_o * O_o.  Every sum is
-// exact (int32 when sum|k| (2^bits - 1) < 2^30, else FP64 below 2^52), so L
-// and Z agree bit for bit with any exact evaluation.
+// is evaluated on D4 orbit sums of pixels, L = sum_o k_o * O_o, or in the
+// packed form on the row-pair sums v(d, c) that make up the orbits, two
+// taps per dot product.  Every sum is exact (int32 when
+// sum|k| (2^bits - 1) < 2^30, else FP64 below 2^52), so L and Z agree bit
+// for bit with any exact evaluation.
 #pragma once
 #include "logfx_internal.h"
 #include "logfx_bits.h"
@@ -501,19 +504,12 @@ template <> struct ZStore<double> {
 // for every outstanding vector memory operation, the strength stores
 // included.
 template <class Acc> constexpr int kMinWaves = std::is_same<Acc, int>::value ? 4 : 1;
-#ifndef LOGFX_P1_CELL_WAVES
-#define LOGFX_P1_CELL_WAVES 3
-#endif
-#ifndef LOGFX_P1_PK_WAVES
-#define LOGFX_P1_PK_WAVES 4
-#endif
 template <class Acc, int MODE, bool LOOP>
 constexpr int kPass1Waves =
     !std::is_same<Acc, int>::value ? kMinWaves<Acc>
     : (MODE & kP1Maps) != 0 ? 2   // inspection only: room for the FP64 map writes
-    : (MODE & kP1Packed) != 0 ? ((MODE & kP1Cells) != 0 || LOOP ? 4 : LOGFX_P1_PK_WAVES)
-    : (MODE & kP1Cells) != 0 ? LOGFX_P1_CELL_WAVES
-    : LOOP ? 3
+    : (MODE & kP1Packed) != 0 ? 4
+    : (MODE & kP1Cells) != 0 || LOOP ? 3
     : kMinWaves<Acc>;
 // The recomputing pass 2 (the fallback without stored strengths) keeps the
 // LoG rings, the deviation rows and the median rows at once.

@@ -24,3 +24,8 @@ def test_kernel_source_hash_is_stable():
     assert h == bench.kernel_source_hash() and len(h) == 16
     assert len(bench.TRAFFIC_SOURCE_HASH) == 16
     assert set(bench.TRAFFIC_BYTES) == {"pass1_kernel", "pass2z_kernel"}
+    # every kernel source outside the gate network's files takes part
+    import glob
+    csrc = os.path.join(ROOT, "paper_1304_3992_amd", "csrc")
+    kernel_files = {os.path.basename(f) for f in glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))}
+    assert set(bench.PIPELINE_SOURCES) == {f for f in kernel_files if not f.startswith("logfx_gate")}
