@@ -156,6 +156,12 @@ def test_adamw_step_matches_oracle(ctx):
         th, m, v = og.adamw(th, gr, m, v, step, 3e-3)
     got = ctx.gate_get_params().astype(np.float64)
     np.testing.assert_allclose(got, th, rtol=1e-5, atol=1e-7)
+    # the step also refreshed the forward kernels' copy of the weights: the
+    # logits follow the stepped parameters
+    feats, _, _ = _net_inputs(6, 96)
+    z = ctx.gate_forward(_bf16_dev(feats)).cpu().numpy().astype(np.float64)
+    z_ref, _ = og.forward(got, feats)
+    np.testing.assert_allclose(z, z_ref, rtol=LOGIT_TOL, atol=LOGIT_TOL)
 
 
 def test_parameters_round_trip_file(ctx, tmp_path):
