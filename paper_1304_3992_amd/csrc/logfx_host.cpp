@@ -566,7 +566,7 @@ int tile_image(logfx_ctx *ctx, const logfx_image *img, const Plan &pl, bool stor
     const long long tx2 = (W + tw2 - 1) / tw2, ty2 = (H + c.rows2 - 1) / c.rows2;
     if (tx1 * ty1 > (1LL << 30) || tx2 * ty2 > (1LL << 30))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "image too large for one launch");
-    if (lds_bytes(c.rows1, kHalo1, pl.rb) > 65536 || (!storez && lds_bytes(c.rows2, kHalo2, pl.rb) > 65536))
+    if (pass1_lds_bytes(c.rows1, pl.rb) > 65536 || (!storez && lds_bytes(c.rows2, kHalo2, pl.rb) > 65536))
         return set_err(ctx, LOGFX_EUNSUPPORTED, "tile configuration exceeds 64 KiB of LDS");
     t.tiles_x1 = (int)tx1, t.ntiles1 = (int)(tx1 * ty1);
     t.tiles_x2 = (int)tx2, t.ntiles2 = (int)(tx2 * ty2);
@@ -669,7 +669,7 @@ int prepare(logfx_ctx *ctx, int n, const logfx_image *imgs, const logfx_params *
         long long slots = 1, crows = 1;
         for (; c.rows1 > 1; --c.rows1) {
             cell_layout(n, imgs, c.pl, c.rows1, slots, crows);
-            if (lds_bytes(c.rows1, kHalo1, c.pl.rb) + 2 * sizeof(unsigned) * slots * crows <= 65536) break;
+            if (pass1_lds_bytes(c.rows1, c.pl.rb) + 2 * sizeof(unsigned) * slots * crows <= 65536) break;
         }
         cell_layout(n, imgs, c.pl, c.rows1, slots, crows);
         c.cell_slots = (int)slots;
@@ -1780,8 +1780,8 @@ int logfx_tune(logfx_ctx *ctx, int32_t n, const logfx_image *imgs, const logfx_p
         for (int round = 0; round < kRounds && rc == LOGFX_OK; ++round)
             for (int i = 0; i < ncand; ++i) {
                 const int rows = cand[i];
-                if (lds_bytes(rows, kHalo1, c.pl.rb) > 65536 && lds_bytes(rows, kHalo2, c.pl.rb) > 65536) continue;
-                ctx->tiles.rows1 = lds_bytes(rows, kHalo1, c.pl.rb) <= 65536 ? rows : saved.rows1;
+                if (pass1_lds_bytes(rows, c.pl.rb) > 65536 && lds_bytes(rows, kHalo2, c.pl.rb) > 65536) continue;
+                ctx->tiles.rows1 = pass1_lds_bytes(rows, c.pl.rb) <= 65536 ? rows : saved.rows1;
                 ctx->tiles.rows2 = lds_bytes(rows, kHalo2, c.pl.rb) <= 65536 ? rows : saved.rows2;
                 double ms[4];
                 if ((rc = measure(ms)) != LOGFX_OK) break;

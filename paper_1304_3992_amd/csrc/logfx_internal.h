@@ -229,5 +229,10 @@ hipError_t noalloc_scratch(int device, void **ptr);
 inline size_t lds_bytes(int rows, int halo, int rb) {
     return (size_t)tile_lds_stride(halo, rb) * (rows + 2 * halo + 2 * rb) * sizeof(uint16_t);
 }
+// Pass 1 holds one spare row after the tile's: its row loop reads each row
+// one step ahead, so the last step reads the row after the tile.
+inline size_t pass1_lds_bytes(int rows, int rb) {
+    return lds_bytes(rows + 1, kHalo1, rb);
+}
 
 }  // namespace logfx

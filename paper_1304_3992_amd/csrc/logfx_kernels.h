@@ -156,16 +156,30 @@ __device__ inline int mul_lo16(int k, pk2 w) {
 // then bounds the kernel.)  For every mask radius these columns lie inside
 // the staged row (its leading alignment columns and trailing padding hold
 // them).
+// The row's LDS words, read apart from their use so that the row loop can
+// issue them a step ahead.
+typedef unsigned RowV4 __attribute__((ext_vector_type(4), aligned(2)));
+struct RowWords {
+    RowV4 a;       // (I-4, I-3) (I-2, I-1) (I0, I1) (I2, I3)
+    unsigned i4;   // I4 (radius 3 and 4)
+};
+template <int RB>
+__device__ inline RowWords read_hrow_pk(const uint16_t *p) {
+    RowWords w;
+    w.a = *(const RowV4 *)(p - 4);
+    w.i4 = pk_words(RB) > 2 ? p[4] : 0u;
+    return w;
+}
+template <int RB>
+__device__ inline void unpack_hrow_pk(const RowWords &w, pk2 (&g)[pk_words(RB)]) {
+    g[0] = as_pk2(w.a.z);
+    g[1] = add_swapped(__builtin_amdgcn_alignbit(w.a.w, w.a.z, 16), w.a.y);   // (I1, I2) + (I-1, I-2)
+    if constexpr (pk_words(RB) > 2)
+        g[2] = add_swapped(__builtin_amdgcn_alignbit(w.i4, w.a.w, 16), w.a.x);   // (I3, I4) + (I-3, I-4)
+}
 template <int RB>
 __device__ inline void load_hrow_pk(const uint16_t *p, pk2 (&g)[pk_words(RB)]) {
-    typedef unsigned V4 __attribute__((ext_vector_type(4), aligned(2)));
-    const V4 a = *(const V4 *)(p - 4);   // (I-4, I-3) (I-2, I-1) (I0, I1) (I2, I3)
-    g[0] = as_pk2(a.z);
-    g[1] = add_swapped(__builtin_amdgcn_alignbit(a.w, a.z, 16), a.y);   // (I1, I2) + (I-1, I-2)
-    if constexpr (pk_words(RB) > 2) {
-        const unsigned i4 = p[4];
-        g[2] = add_swapped(__builtin_amdgcn_alignbit(i4, a.w, 16), a.x);   // (I3, I4) + (I-3, I-4)
-    }
+    unpack_hrow_pk<RB>(read_hrow_pk<RB>(p), g);
 }
 
 // Both LoG responses of the centre row of the packed ring (ring row RB):
@@ -528,7 +542,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     // touches (a.cell_slots of them), in the dynamic LDS after the tile: a
     // fixed array for the worst case (248 one-pixel cells) would push the
     // workgroup past a quarter of the CU's LDS
-    unsigned *const cellv = reinterpret_cast<unsigned *>(lds + Strip<kHalo1, RB>::stride * (a.rows + 2 * kHalo1 + 2 * RB));
+    unsigned *const cellv = reinterpret_cast<unsigned *>(lds + Strip<kHalo1, RB>::stride * (a.rows + 1 + 2 * kHalo1 + 2 * RB));
     unsigned *const cellc = cellv + a.cell_rows * a.cell_slots;
     constexpr int HL = kHalo1, P = 2 * RB + 1;
     // The step schedule below takes one halo row above and below the strip:
@@ -562,6 +576,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     const int nsteps = g.Rv + 2 * HL;
     const int t0 = g.y0 - HL;
     const uint16_t *lrow = lds + (2 * RB) * g.stride + g.lc;   // LDS row of step si
+    // packed form: the words of the next step's row, read one step ahead
+    // (the last step's read lands in the spare LDS row after the tile); the
+    // cell-summing variants of the two widest radius pairs would spill the
+    // five registers it holds and read each row in its step
+    constexpr bool AHEAD = PK && ((MODE & kP1Cells) == 0 || RA + RB < 7);
+    RowWords ahead{};
+    if constexpr (AHEAD) ahead = read_hrow_pk<RB>(lrow);
 
     // Feature mode: the image is cut into CY x CX cells, CY = 2^cells_ly,
     // CX = 2^cells_lx (row r and column x belong to cell (r * CY / H,
@@ -628,7 +649,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             for (int s = 0; s < P - 1; ++s)
 #pragma unroll
                 for (int m = 0; m < pk_words(RB); ++m) hp[s][m] = hp[s + 1][m];
-            load_hrow_pk<RB>(lrow, hp[P - 1]);
+            if constexpr (AHEAD) {
+                unpack_hrow_pk<RB>(ahead, hp[P - 1]);
+                ahead = read_hrow_pk<RB>(lrow + g.stride);
+            } else {
+                load_hrow_pk<RB>(lrow, hp[P - 1]);
+            }
             log_pair_pk<RA, RB>(hp, a.taps, Ln);
         } else {
 #pragma unroll
@@ -894,7 +920,7 @@ hipError_t occupancy(K k, size_t shm, int *max_grid) {
 
 template <class Acc, int RA, int RB, int MODE>
 hipError_t p1(const Pass1Args<typename AccOps<Acc>::Taps> &a, int grid, hipStream_t s, int *max_grid) {
-    const size_t shm = lds_bytes(a.rows, kHalo1, RB) +
+    const size_t shm = pass1_lds_bytes(a.rows, RB) +
                        ((MODE & kP1Cells) != 0 ? 2 * sizeof(unsigned) * a.cell_rows * a.cell_slots : 0);
     // the map-writing and feature variants always run one tile per workgroup
     if constexpr ((MODE & (kP1Maps | kP1Cells)) != 0) {
