@@ -203,8 +203,12 @@ __device__ inline void log_pair_pk(const pk2 (&g)[2 * RB + 1][pk_words(RB)], con
     out[1] = l1;
 }
 
-// Opposite strict signs of p and q.
-__device__ inline bool opposite(int p, int q) { return (min(p, q) < 0) & (max(p, q) > 0); }
+// Opposite strict signs of p and q: the exact 64-bit product p q is
+// negative, i.e. its high word is.  (Written without min / max, so that the
+// crossing rule shares none with it and takes its five-value extremes in
+// two three-input operations; the compiler keeps this test in the branch
+// taken only when the wave has a zero pixel.)
+__device__ inline bool opposite(int p, int q) { return __mulhi(p, q) < 0; }
 __device__ inline bool opposite(double p, double q) { return p * q < 0.0; }
 
 // Zero-crossing strength (Sec. 3.2) of centre a with neighbours up, dn, lf,

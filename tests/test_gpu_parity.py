@@ -36,8 +36,28 @@ def _scene_crop(h, w, seed=1, bits=8):
                                noise_sigma=12.0, sp_density=0.05, bits=bits)
 
 
+def _zero_pixel_steps():
+    """Noise-free three-level steps, 0 | 50 | 100 across plus 0 | 40 | 80
+    down: the middle column and row are centres of antisymmetry, so with
+    zero-sum masks the LoG is exactly 0 on them (away from where they
+    cross) between neighbours of opposite signs -- the crossing rule's
+    zero-pixel case, left / right and up / down -- beside flat areas of
+    exact zeros."""
+    a = np.zeros(300, np.int32)
+    a[101] = 50
+    a[102:] = 100
+    b = np.zeros(150, np.int32)
+    b[70] = 40
+    b[71:] = 80
+    img = b[:, None] + a[None, :]
+    img[20:40, 200:230] += 30
+    return img.astype(np.uint8)
+
+
 MAP_CASES = [
     # (name, image factory, bits, mask pair, grid bits)
+    ("zero_pixel_rule", _zero_pixel_steps, 0, ((5, 0.8), (9, 1.4)), 16),
+    ("zero_pixel_rule_r1r3", _zero_pixel_steps, 0, ((3, 0.5), (7, 1.0)), 16),
     ("c1crop_u8", lambda: scenes.config1()[:300, :250], 0, ((5, 0.8), (9, 1.4)), 16),
     ("rand_u8_ragged", lambda: _rand((131, 301), 255, 3, np.uint8), 0, ((5, 0.8), (9, 1.4)), 16),
     ("scene_u11", lambda: _scene_crop(200, 333, 5, 11), 11, ((5, 0.8), (9, 1.4)), 16),
@@ -82,6 +102,7 @@ PACKED_CASES = [
     ("u12_r3r3", lambda: _rand((75, 140), 4095, 43, np.uint16), 12, ((7, 1.0), (7, 1.2)), 15, True),
     ("u12_r4r4_wide", lambda: _rand((60, 500), 4095, 44, np.uint16), 12, ((9, 1.4), (9, 2.0)), 12, True),
     ("u8_r1r1", lambda: _rand((65, 129), 255, 45, np.uint8), 0, ((3, 0.5), (3, 0.9)), 16, True),
+    ("zero_pixel_rule", _zero_pixel_steps, 0, ((5, 0.8), (9, 1.4)), 16, True),
     # 14-bit pixels on a 12-bit tap grid: exact in int32, but four pixels
     # overflow int16, so the 32-bit form runs whatever the option says
     ("u14_grid12_r2r4", lambda: _rand((70, 300), 16383, 46, np.uint16), 14, ((5, 0.8), (9, 1.4)), 12, False),
