@@ -475,12 +475,15 @@ __device__ inline void for_each_tile(int total, F &&f) {
     }
 }
 
-// acc + 1 in the lanes of mask (a wave's ballot): one add with the mask as
-// carry-in
-__device__ inline unsigned add_lanes(unsigned acc, uint64_t mask) {
+// acc + [z != 0] per lane, and the wave's lane mask of z != 0: one compare
+// whose mask is the carry-in of one add.  (Written as C, the compiler keeps
+// the compare's mask across the strength store's branch and rebuilds it as
+// 0 / 1 in a register before adding.)
+__device__ inline unsigned count_nonzero(unsigned acc, int z, uint64_t &mask) {
     unsigned r;
     uint64_t co;
-    asm("v_addc_co_u32 %0, %1, 0, %2, %3" : "=v"(r), "=s"(co) : "v"(acc), "s"(mask));
+    asm("v_cmp_ne_u32_e64 %1, 0, %3\n\tv_addc_co_u32 %0, %2, 0, %4, %1"
+        : "=v"(r), "=&s"(mask), "=s"(co) : "v"(z), "v"(acc));
     return r;
 }
 
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         return (int)floor((double)n * cells / (double)d);
     };
     unsigned fv = 0;            // value sum
-    unsigned fc1 = 0, fc2 = 0;  // crossings of mask 1, of mask 2
+    unsigned fc[2] = {0, 0};    // crossings of mask 1, of mask 2
     int fcy = 0, fat = 0;       // current cell row (vector register); its slot row's first slot
     int fslot = 0;              // the slot of the lane's cell column (output lanes)
     int fend = 0;               // the strip row that ends the current cell row
@@ -626,12 +629,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
         fend = min(cell_end(fcy0), flast);
     }
     auto flush = [&](const int r) __attribute__((always_inline)) {
-        if (g.outc && (fv | fc1 | fc2)) {
+        if (g.outc && (fv | fc[0] | fc[1])) {
             const int at = fat + fslot;
             atomicAdd(&cellv[at], fv);
-            atomicAdd(&cellc[at], fc1 | fc2 << 16);
+            atomicAdd(&cellc[at], fc[0] | fc[1] << 16);
         }
-        fv = fc1 = fc2 = 0;
+        fv = fc[0] = fc[1] = 0;
         // the cell row of row r + 1 (cells may be empty when H < cells):
         // the first c > fcy whose rows reach past r, by shifts only
         int cy = fcy + 1;
@@ -686,7 +689,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             const double z = AccOps<Acc>::to_d(zr[j]);
             sz[j] += z;
             sq[j] = __fma_rn(z, z, sq[j]);
-            cnt[j] += __popcll(__ballot(zr[j] != Acc(0)));   // wave-uniform
+            if constexpr ((MODE & kP1Cells) != 0 && std::is_same<Acc, int>::value) {
+                // the cell's crossing count and the wave's in one compare
+                uint64_t nz;
+                fc[j] = count_nonzero(fc[j], zr[j], nz);
+                cnt[j] += __popcll(nz);   // wave-uniform
+            } else {
+                cnt[j] += __popcll(__ballot(zr[j] != Acc(0)));   // wave-uniform
+                if constexpr ((MODE & kP1Cells) != 0) fc[j] += (unsigned)(zr[j] != Acc(0));
+            }
             if constexpr ((MODE & kP1Maps) != 0) {
                 if (use) {
                     const long long at = (long long)r * g.W + g.xc;
@@ -707,9 +718,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
             // pixel (r, xc): the centre of ring row RB - 1
             if constexpr (PK) fv += as_u32(hp[RB - 1][0]) & 0xFFFFu;
             else fv += (unsigned)h[RB - 1][0];
-            fc1 = add_lanes(fc1, __ballot(zr[0] != Acc(0)));
-            fc2 = add_lanes(fc2, __ballot(zr[1] != Acc(0)));
-            if (si < 2) fv = fc1 = fc2 = 0;
+            if (si < 2) fv = fc[0] = fc[1] = 0;
             else if (r == fend) flush(r);
         }
     };
