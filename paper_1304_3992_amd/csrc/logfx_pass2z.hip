@@ -223,10 +223,20 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
             }
         };
         auto run = [&](auto clamp) __attribute__((always_inline)) {
+            // The last 2 HL rows this tile reads are the first ones the tile
+            // below it reads: they are loaded first, so that the two tiles,
+            // dispatched close together on one XCD, read them at about the
+            // same time and the second read finds them in the L2.
+            ZT tail[2 * HL];
+#pragma unroll
+            for (int k = 0; k < 2 * HL; ++k) {
+                const int row = min(max(y0 + Rv - HL + k, 0), H - 1);
+                tail[k] = zcol[(long long)row * W];
+            }
             // full groups unrolled (loads first, the ring rotates by
-            // renaming), the rest one step at a time
+            // renaming), the rest one step at a time, then the tail rows
             int si0 = 0;
-            for (; si0 + G <= nsteps; si0 += G) {
+            for (; si0 + G <= Rv; si0 += G) {
                 ZT q[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
@@ -238,10 +248,13 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
                 // E bits wb .. wb + 35 present: the word's 32 output rows are final
                 if (si0 + G - 2 * WR - wb >= 36) emit(32);
             }
-            for (; si0 < nsteps; ++si0) {
+            for (; si0 < Rv; ++si0) {
                 const int row = min(max(y0 - HL + si0, 0), H - 1);
                 step(si0, zcol[(long long)row * W], clamp);
             }
+            // (at most 35 + G - 1 + 2 HL < 64 E bits are pending here)
+#pragma unroll
+            for (int k = 0; k < 2 * HL; ++k) step(Rv + k, tail[k], clamp);
         };
         // the E rows y0-2 .. y0+Rv+1 the output uses lie inside the image:
         // no row clamping of the extracted bits
