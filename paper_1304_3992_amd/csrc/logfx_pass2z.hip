@@ -197,6 +197,34 @@ __global__ __launch_bounds__(256) void pass2z_kernel(Pass2Args<typename AccOps<A
                     Wq[j][NR - 1] = wq;
                 }
             }
+            if constexpr (!C && MED >= 0) {
+                // Interior strips: E as a sign bit.  dev > thr exactly when
+                // thr - dev < 0 (finite values; their difference is 0 only
+                // when they are equal, and then +0), so bit 31 of the high
+                // word of thr - dev is E_j, and the words combine by AND
+                // (the 5x5 stage) and OR (the two masks) before the bit is
+                // moved into place: no lane masks and selects per row.  (Not
+                // in the gated kernels, which hold two tile forms and would
+                // lose occupancy to the registers this schedule takes.)
+                unsigned eb = 0;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const double s3[3] = {Zs[j][WR - 1], Zs[j][WR], Zs[j][WR + 1]};
+                    const double q3[3] = {Zq[j][WR - 1], Zq[j][WR], Zq[j][WR + 1]};
+                    unsigned e = (unsigned)__double2hiint((j == 0 ? thr72_0 : thr72_1) - dev_72var(s3, q3));
+                    if constexpr (S5)
+                        e &= (unsigned)__double2hiint((j == 0 ? thr600_0 : thr600_1) - dev_600var(Ws[j], Wq[j]));
+                    eb |= e;
+                }
+                if (si >= 2 * WR) {
+                    const int p = si - 2 * WR - wb;   // its bit in elo:ehi (wave-uniform)
+                    const unsigned mlo = p < 32 ? 1u << p : 0u, mhi = p >= 32 ? 1u << (p - 32) : 0u;
+                    const unsigned spread = (unsigned)((int)eb >> 31);   // E ? ~0 : 0
+                    elo |= spread & mlo;
+                    ehi |= spread & mhi;
+                }
+                return;
+            }
             bool ej = false;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {   // deviations of Z around the middle row of the ring
