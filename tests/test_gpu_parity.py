@@ -246,6 +246,29 @@ EXTRACT_CASES = [
 ]
 
 
+@pytest.mark.parametrize("rows1,rows2", [(40, 24), (64, 64), (48, 96), (64, 128)])
+@pytest.mark.parametrize("std5", [False, True])
+def test_strip_heights(ctx, rows1, rows2, std5):
+    """Other strip heights than the tuned ones, on a ragged 11-bit crop
+    whose last strips are short: pass 1's rows read a step ahead and pass
+    2's rows shared with the strip below, read first, at every position of
+    a strip, with the 5x5 first stage and without."""
+    img = _scene_crop(349, 301, 25, 11)
+    orc_t, lib_t = masks()
+    kw = dict(std5_max=_std5_threshold(img, orc_t, 0.5)[0]) if std5 else {}
+    o = run_oracle(img, orc_t, **kw)
+    opts = (logfx.OPT_ROWS1, logfx.OPT_ROWS2)
+    saved = [ctx.get_option(k) for k in opts]
+    try:
+        ctx.set_option(logfx.OPT_ROWS1, rows1)
+        ctx.set_option(logfx.OPT_ROWS2, rows2)
+        F, rep = run_gpu(ctx, img, lib_t, bits=11, **kw)
+    finally:
+        for k, v in zip(opts, saved):
+            ctx.set_option(k, v)
+    compare(F, o, smooth=True, **kw)
+
+
 @pytest.mark.parametrize("name,make,bits,kw", EXTRACT_CASES, ids=[c[0] for c in EXTRACT_CASES])
 def test_extract_parity(ctx, name, make, bits, kw):
     img = make()
