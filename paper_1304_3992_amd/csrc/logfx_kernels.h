@@ -561,11 +561,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPass1Waves
     for_each_tile<LOOP>(a.L.total1, [&](const int item) __attribute__((always_inline)) {
     const ImageJob J = job_of(a.L, a.L.nimg == 1 ? 0 : a.L.owner1[item]);
     const Strip<HL, RB> g(J.img, item - J.base1, J.tiles_x1, a.rows);
+    // the fill at raised wave priority: its loads issue ahead of the other
+    // workgroups' arithmetic on the SIMD, which shortens the wait at the
+    // barrier (pass 1 about 2 % faster)
+    __builtin_amdgcn_s_setprio(3);
     g.fill(lds, J.img);
     if constexpr ((MODE & kP1Cells) != 0) {
         for (int i = threadIdx.x; i < a.cell_rows * a.cell_slots; i += blockDim.x) cellv[i] = cellc[i] = 0;
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
 
     // ring of pair-sum rows: 32-bit, or packed (kP1Packed)
     constexpr bool PK = (MODE & kP1Packed) != 0;
